@@ -1,0 +1,187 @@
+/*
+ * bmotor.h -- C ABI of libbmotor: Monte Carlo integration of Brownian-motor
+ * Langevin equations on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (Spiechowicz, Kostur & Machura, "GPU accelerated Monte Carlo
+ * simulation of Brownian motors dynamics with CUDA"):
+ *   - eq. (24):  x' = -V'(x) + eta(t) + Gamma(t) + xi(t)   (overdamped), and the
+ *     inertial form  x'' + gamma x' = -V'(x) + a cos(omega t) + F + noise;
+ *   - Algorithm 1: weak order 2.0 predictor-corrector step, three drift
+ *     evaluations per step;
+ *   - Algorithm 2 / eq. (25): simplified three-point Gaussian increment;
+ *   - Algorithm 3 / eqs. (3)-(8), (26)-(27): white Poissonian increment on the
+ *     jump-adapted grid;
+ *   - Algorithm 4 / eqs. (13)-(17), (29)-(30): dichotomous increment;
+ *   - Sec. 4 (Instruction optimization): x kept modulo L, periods counted apart;
+ *   - eq. (31): <v> = < (x(t_f) - x(t_i)) / (t_f - t_i) > over the ensemble.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.   The caller owns all device memory.  Pointers named d_* are device
+ *           pointers (e.g. torch tensors' data_ptr()), h_* are host pointers.
+ *           The library never allocates device memory for user data; a handle
+ *           owns only host-side metadata.  A workspace must outlive every handle
+ *           created on it and every call enqueued with it.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *           Device work is enqueued asynchronously on it; results are valid once
+ *           the stream has been synchronised.  Host structs are read during the
+ *           call only.
+ * Errors.   Every int-returning call returns BM_OK (0) or a negative BM_ERR_*.
+ *           Arguments are validated before anything is enqueued; on error
+ *           nothing is enqueued and no state changes.  bm_last_error() gives a
+ *           message for the calling thread's last failure.  Non-finite path
+ *           velocities are counted in bm_stats, not reported as errors.
+ * Threads.  A handle is not thread-safe; distinct handles are independent.
+ * Randomness. Counter-based Philox4x32-10 (Salmon et al., SC'11), key = seed,
+ *           counter = (block, path, point, stream tag).  Results depend only on
+ *           (model, run, path index, step index): never on launch shape, chunking
+ *           or which other paths run alongside.
+ */
+#ifndef BMOTOR_H
+#define BMOTOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BM_ABI_VERSION 1u
+
+/* return codes */
+#define BM_OK               0
+#define BM_ERR_INVALID_ARG (-1)  /* NULL pointer, bad size field, out-of-range parameter */
+#define BM_ERR_UNSUPPORTED (-2)  /* valid but outside what the kernels implement           */
+#define BM_ERR_WORKSPACE   (-3)  /* workspace too small or misaligned (256 B)              */
+#define BM_ERR_DEVICE      (-4)  /* no usable gfx950 device, or a HIP call failed          */
+#define BM_ERR_STATE       (-5)  /* call not valid in the handle's current state           */
+
+/* bm_model.dyn */
+#define BM_OVERDAMPED 0u   /* eq. (24)                                                     */
+#define BM_INERTIAL   1u   /* x'' + gamma x' = -V'(x) + a cos(omega t) + F + noise         */
+
+/* bm_model.pot: the periodic potential V(x) and its period L */
+#define BM_POT_SIN     0u  /* V = sin(2 pi x), L = 1                                       */
+#define BM_POT_RATCHET 1u  /* V = -sin(2 pi x) - sin(4 pi x)/4, L = 1                      */
+#define BM_POT_TENT    2u  /* eq. (2): V = 1 + x on [-1,0), 1 - x on [0,1], L = 2          */
+#define BM_POT_FREE    3u  /* V = 0 (L = 1 for the folding)                                */
+
+/* bm_model.noise: bit mask */
+#define BM_NOISE_GAUSS   1u  /* xi: Gaussian white noise, Algorithm 2                       */
+#define BM_NOISE_POISSON 2u  /* eta: white Poissonian noise, Algorithm 3                    */
+#define BM_NOISE_DICH    4u  /* Gamma: dichotomous noise, Algorithm 4                       */
+
+/* bm_run.prec: arithmetic of the path state (statistics are always FP64) */
+#define BM_F64 0u
+#define BM_F32 1u
+
+typedef struct bm_model {
+    uint32_t size;         /* = sizeof(bm_model)                                          */
+    uint32_t dyn;          /* BM_OVERDAMPED | BM_INERTIAL                                 */
+    uint32_t pot;          /* BM_POT_*                                                    */
+    uint32_t noise;        /* BM_NOISE_* mask                                             */
+    double gamma;          /* friction (inertial only), > 0                               */
+    double drive_amp;      /* a in a cos(omega t); needs steps_per_period > 0 if != 0     */
+    double drive_omega;    /* omega > 0 when steps_per_period > 0                         */
+    double force;          /* constant tilt F                                             */
+    double D;              /* Gaussian intensity D_G >= 0: G = sqrt(2D) (overdamped),
+                              sqrt(2 gamma D) (inertial)                                   */
+    double shot_rate;      /* lambda > 0, eq. (4)                                         */
+    double shot_mean;      /* zeta >= 0, eq. (5); bias a = lambda zeta, eq. (6)            */
+    double dich_Fa;        /* eq. (13): level -Fa (Fa >= 0)                                */
+    double dich_Fb;        /* eq. (13): level +Fb (Fb >= 0)                                */
+    double dich_mua;       /* eq. (14): rate of leaving -Fa, > 0                           */
+    double dich_mub;       /* eq. (14): rate of leaving +Fb, > 0                           */
+} bm_model;
+
+typedef struct bm_run {
+    uint32_t size;             /* = sizeof(bm_run)                                         */
+    uint32_t prec;             /* BM_F64 | BM_F32                                          */
+    uint32_t steps_per_period; /* spp > 0: dt = (2 pi / omega) / spp and the drive phase is
+                                  the integer step index mod spp; 0: no periodic drive      */
+    uint32_t point_id;         /* parameter-point index in the random-stream counter        */
+    double dt;                 /* time step if spp == 0 (> 0); must be 0 if spp > 0         */
+    uint64_t n_steps;          /* horizon t_f = n_steps dt (used by bm_scan)                */
+    uint64_t window_start;     /* eq. (31): t_i = window_start dt                           */
+    uint64_t n_paths;          /* 1 .. 2^32 - 1                                             */
+    uint64_t seed;             /* Philox key                                                */
+    double x0_lo, x0_hi;       /* x(0) ~ U[x0_lo, x0_hi)                                    */
+    double v0_lo, v0_hi;       /* v(0) ~ U[v0_lo, v0_hi) (inertial)                         */
+} bm_run;
+
+typedef struct bm_stats {
+    uint64_t n;            /* paths with a finite velocity                                */
+    uint64_t n_nonfinite;  /* paths whose velocity is NaN or infinite                     */
+    double mean;           /* <v>, eq. (31)                                               */
+    double var;            /* unbiased sample variance of the per-path velocities          */
+    double se;             /* standard error sqrt(var / n)                                 */
+    double t_window;       /* t_f - t_i used                                               */
+} bm_stats;
+
+typedef struct bm_tune {
+    uint32_t size;            /* = sizeof(bm_tune)                                         */
+    uint32_t paths_per_lane;  /* 1 or 2                                                    */
+    uint32_t block;           /* work-group size: 64, 128, 256, 512                         */
+    uint32_t reserved;
+} bm_tune;
+
+typedef struct bm_ensemble bm_ensemble;
+
+/* Library version of this header (BM_ABI_VERSION). */
+uint32_t bm_abi_version(void);
+
+/* Message of the calling thread's last failed call ("" if none).  The pointer
+ * stays valid until that thread's next call into the library. */
+const char *bm_last_error(void);
+
+/* Bytes of device workspace an ensemble of (model, run) needs (multiple of 256). */
+int bm_ensemble_workspace_size(const bm_model *model, const bm_run *run, size_t *bytes);
+
+/* Create an ensemble of run->n_paths independent realisations on the workspace
+ * d_ws (256-byte aligned, >= bm_ensemble_workspace_size bytes) and enqueue the
+ * initial conditions on `stream`: x(0), v(0) uniform, Poisson countdown
+ * s = floor(E / (lambda dt)) with E ~ Exp(1), dichotomous state drawn from its
+ * stationary law Pr{+Fb} = mu_a / (mu_a + mu_b) and entered at step 0.
+ * The drive table (a cos(2 pi k / spp) + F in FP64) is uploaded from host memory
+ * and create returns once that copy is complete (it synchronises `stream`).
+ * The handle is written to *out.  BM_ERR_DEVICE if no gfx950 device is usable. */
+int bm_ensemble_create(const bm_model *model, const bm_run *run, void *d_ws, size_t ws_bytes,
+                       void *stream, bm_ensemble **out);
+
+/* Release the handle (host metadata only; the workspace stays the caller's). */
+int bm_ensemble_destroy(bm_ensemble *e);
+
+/* Choose the launch shape (NULL restores the default).  Results never depend on it. */
+int bm_ensemble_set_tune(bm_ensemble *e, const bm_tune *tune);
+
+/* Advance every path by n_steps steps of Algorithm 1 (with Algorithms 2-4 for
+ * the enabled noises), enqueued on the ensemble's stream.  Resumable: any
+ * split of a horizon into calls gives bit-identical states.  The position at
+ * step window_start is recorded for eq. (31). */
+int bm_integrate(bm_ensemble *e, uint64_t n_steps);
+
+/* Steps integrated so far (host-side counter; no synchronisation). */
+int bm_ensemble_steps(const bm_ensemble *e, uint64_t *n_done);
+
+/* Enqueue the FP64 ensemble reduction of eq. (31) over the current state:
+ * per path v_p = ((w - w_i) L + (x - x_i)) / ((n - n_i) dt), then count, mean,
+ * unbiased variance and standard error with compensated (double-double) sums in
+ * a fixed order (independent of the launch shape).  Writes one bm_stats to the
+ * device pointer d_out.  BM_ERR_STATE unless steps done > window_start. */
+int bm_reduce(bm_ensemble *e, bm_stats *d_out);
+
+/* Enqueue a copy of paths [first, first + count) to device arrays (any may be
+ * NULL): d_x unwrapped position w L + x (FP64), d_v velocity (FP64),
+ * d_noise 5 x int64 per path: Poisson countdown, Poisson kicks so far,
+ * dichotomous countdown, dichotomous flips so far, dichotomous state (0: -Fa,
+ * 1: +Fb).  d_vp (FP64) receives the eq. (31) per-path velocity once
+ * steps done > window_start (else it is left untouched). */
+int bm_read_paths(bm_ensemble *e, uint64_t first, uint64_t count,
+                  double *d_x, double *d_v, int64_t *d_noise, double *d_vp);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BMOTOR_H */

@@ -1,0 +1,260 @@
+"""ctypes binding of libbmotor (include/bmotor.h): argument marshalling only.
+
+Every step of the Monte Carlo path runs in the HIP kernels of libbmotor.so; this
+module mirrors the C structs, forwards calls under the same names, and (in
+``Ensemble``) allocates the caller-owned workspace as a torch tensor on the
+current device and passes torch's current stream.  If the in-tree library is
+missing the import fails: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbmotor.so")
+
+BM_OK = 0
+BM_ERR_INVALID_ARG = -1
+BM_ERR_UNSUPPORTED = -2
+BM_ERR_WORKSPACE = -3
+BM_ERR_DEVICE = -4
+BM_ERR_STATE = -5
+
+BM_OVERDAMPED, BM_INERTIAL = 0, 1
+BM_POT_SIN, BM_POT_RATCHET, BM_POT_TENT, BM_POT_FREE = 0, 1, 2, 3
+BM_NOISE_GAUSS, BM_NOISE_POISSON, BM_NOISE_DICH = 1, 2, 4
+BM_F64, BM_F32 = 0, 1
+
+
+class bm_model(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("dyn", ctypes.c_uint32), ("pot", ctypes.c_uint32),
+                ("noise", ctypes.c_uint32), ("gamma", ctypes.c_double), ("drive_amp", ctypes.c_double),
+                ("drive_omega", ctypes.c_double), ("force", ctypes.c_double), ("D", ctypes.c_double),
+                ("shot_rate", ctypes.c_double), ("shot_mean", ctypes.c_double),
+                ("dich_Fa", ctypes.c_double), ("dich_Fb", ctypes.c_double),
+                ("dich_mua", ctypes.c_double), ("dich_mub", ctypes.c_double)]
+
+
+class bm_run(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("prec", ctypes.c_uint32),
+                ("steps_per_period", ctypes.c_uint32), ("point_id", ctypes.c_uint32),
+                ("dt", ctypes.c_double), ("n_steps", ctypes.c_uint64), ("window_start", ctypes.c_uint64),
+                ("n_paths", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("x0_lo", ctypes.c_double), ("x0_hi", ctypes.c_double),
+                ("v0_lo", ctypes.c_double), ("v0_hi", ctypes.c_double)]
+
+
+class bm_stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("n_nonfinite", ctypes.c_uint64), ("mean", ctypes.c_double),
+                ("var", ctypes.c_double), ("se", ctypes.c_double), ("t_window", ctypes.c_double)]
+
+
+class bm_tune(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("paths_per_lane", ctypes.c_uint32),
+                ("block", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+STATS_BYTES = ctypes.sizeof(bm_stats)
+
+
+class BMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("libbmotor error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+# (name, restype, argtypes) of every entry point declared in include/bmotor.h
+_vp, _sz = ctypes.c_void_p, ctypes.c_size_t
+_P = ctypes.POINTER
+SIGNATURES = [
+    ("bm_abi_version", ctypes.c_uint32, []),
+    ("bm_last_error", ctypes.c_char_p, []),
+    ("bm_ensemble_workspace_size", ctypes.c_int, [_P(bm_model), _P(bm_run), _P(_sz)]),
+    ("bm_ensemble_create", ctypes.c_int, [_P(bm_model), _P(bm_run), _vp, _sz, _vp, _P(_vp)]),
+    ("bm_ensemble_destroy", ctypes.c_int, [_vp]),
+    ("bm_ensemble_set_tune", ctypes.c_int, [_vp, _P(bm_tune)]),
+    ("bm_integrate", ctypes.c_int, [_vp, ctypes.c_uint64]),
+    ("bm_ensemble_steps", ctypes.c_int, [_vp, _P(ctypes.c_uint64)]),
+    ("bm_reduce", ctypes.c_int, [_vp, _vp]),
+    ("bm_read_paths", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_uint64, _vp, _vp, _vp, _vp]),
+]
+
+
+def lib() -> ctypes.CDLL:
+    """Load the in-tree libbmotor.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libbmotor.so not built (run python -m paper_1409_4923_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().bm_last_error().decode()
+
+
+def check(rc: int) -> None:
+    if rc != BM_OK:
+        raise BMError(rc, last_error())
+
+
+def make_model(**kw) -> bm_model:
+    m = bm_model()
+    m.size = ctypes.sizeof(bm_model)
+    m.gamma, m.drive_omega, m.dich_mua, m.dich_mub, m.shot_rate = 1.0, 1.0, 1.0, 1.0, 1.0
+    for k, v in kw.items():
+        setattr(m, k, v)
+    return m
+
+
+def make_run(**kw) -> bm_run:
+    r = bm_run()
+    r.size = ctypes.sizeof(bm_run)
+    r.x0_hi = 1.0
+    r.n_paths = 1
+    for k, v in kw.items():
+        setattr(r, k, v)
+    return r
+
+
+def make_tune(paths_per_lane: int = 1, block: int = 256) -> bm_tune:
+    t = bm_tune()
+    t.size = ctypes.sizeof(bm_tune)
+    t.paths_per_lane = paths_per_lane
+    t.block = block
+    return t
+
+
+# ---------------------------------------------------------------------------
+# Same-name thin wrappers (raise BMError on failure)
+# ---------------------------------------------------------------------------
+def bm_abi_version() -> int:
+    return int(lib().bm_abi_version())
+
+
+def bm_ensemble_workspace_size(model: bm_model, run: bm_run) -> int:
+    n = ctypes.c_size_t()
+    check(lib().bm_ensemble_workspace_size(ctypes.byref(model), ctypes.byref(run), ctypes.byref(n)))
+    return int(n.value)
+
+
+def bm_ensemble_create(model: bm_model, run: bm_run, d_ws: int, ws_bytes: int, stream: int) -> int:
+    h = ctypes.c_void_p()
+    check(lib().bm_ensemble_create(ctypes.byref(model), ctypes.byref(run), d_ws, ws_bytes, stream,
+                                   ctypes.byref(h)))
+    return int(h.value)
+
+
+def bm_ensemble_destroy(h: int) -> None:
+    check(lib().bm_ensemble_destroy(h))
+
+
+def bm_ensemble_set_tune(h: int, tune: bm_tune | None) -> None:
+    check(lib().bm_ensemble_set_tune(h, ctypes.byref(tune) if tune is not None else None))
+
+
+def bm_integrate(h: int, n_steps: int) -> None:
+    check(lib().bm_integrate(h, n_steps))
+
+
+def bm_ensemble_steps(h: int) -> int:
+    n = ctypes.c_uint64()
+    check(lib().bm_ensemble_steps(h, ctypes.byref(n)))
+    return int(n.value)
+
+
+def bm_reduce(h: int, d_out: int) -> None:
+    check(lib().bm_reduce(h, d_out))
+
+
+def bm_read_paths(h: int, first: int, count: int, d_x: int | None, d_v: int | None,
+                  d_noise: int | None, d_vp: int | None) -> None:
+    check(lib().bm_read_paths(h, first, count, d_x, d_v, d_noise, d_vp))
+
+
+# ---------------------------------------------------------------------------
+# Convenience owner of a workspace (torch device memory + current stream)
+# ---------------------------------------------------------------------------
+@dataclass
+class PathState:
+    x: "object"       # unwrapped position, float64 tensor
+    v: "object"       # velocity, float64 tensor
+    noise: "object"   # int64 [count, 5]: sP, kP, sD, mD, d
+    vp: "object"      # eq. (31) per-path velocity (NaN until the window is open)
+
+
+class Ensemble:
+    """An ensemble of paths living in a torch-allocated workspace on the current GPU."""
+
+    def __init__(self, model: bm_model, run: bm_run, tune: bm_tune | None = None, device=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        self.model, self.run = model, run
+        self.ws_bytes = bm_ensemble_workspace_size(model, run)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.h = bm_ensemble_create(model, run, self.ws.data_ptr(), self.ws_bytes, self.stream.cuda_stream)
+        if tune is not None:
+            bm_ensemble_set_tune(self.h, tune)
+
+    def close(self):
+        if getattr(self, "h", None):
+            bm_ensemble_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tune(self, tune: bm_tune | None):
+        bm_ensemble_set_tune(self.h, tune)
+
+    def integrate(self, n_steps: int):
+        bm_integrate(self.h, n_steps)
+
+    @property
+    def steps(self) -> int:
+        return bm_ensemble_steps(self.h)
+
+    def reduce(self, out=None):
+        """Enqueue the reduction; returns the raw 48-byte device tensor holding bm_stats."""
+        torch = self.torch
+        if out is None:
+            out = torch.empty(STATS_BYTES, dtype=torch.uint8, device=self.device)
+        bm_reduce(self.h, out.data_ptr())
+        return out
+
+    def stats(self) -> bm_stats:
+        raw = self.reduce()
+        self.stream.synchronize()
+        return stats_from_bytes(raw.cpu().numpy().tobytes())
+
+    def read(self, first: int = 0, count: int | None = None) -> PathState:
+        torch = self.torch
+        count = self.run.n_paths - first if count is None else count
+        x = torch.empty(count, dtype=torch.float64, device=self.device)
+        v = torch.empty(count, dtype=torch.float64, device=self.device)
+        nz = torch.empty((count, 5), dtype=torch.int64, device=self.device)
+        vp = torch.full((count,), float("nan"), dtype=torch.float64, device=self.device)
+        bm_read_paths(self.h, first, count, x.data_ptr(), v.data_ptr(), nz.data_ptr(), vp.data_ptr())
+        self.stream.synchronize()
+        return PathState(x.cpu(), v.cpu(), nz.cpu(), vp.cpu())
+
+
+def stats_from_bytes(b: bytes) -> bm_stats:
+    s = bm_stats()
+    ctypes.memmove(ctypes.byref(s), b, STATS_BYTES)
+    return s

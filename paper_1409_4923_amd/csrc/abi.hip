@@ -1,0 +1,476 @@
+// abi.hip -- libbmotor C ABI: argument validation, workspace layout, launch
+// sequencing, and the fixed-order FP64 ensemble reduction (eq. 31).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bmotor.h"
+#include "common.hpp"
+#include "launch.hpp"
+
+using namespace bm;
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+static int ok()
+{
+    g_err.clear();
+    return BM_OK;
+}
+
+static int hip_fail(hipError_t e, const char *what)
+{
+    return fail(BM_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" uint32_t bm_abi_version(void) { return BM_ABI_VERSION; }
+extern "C" const char *bm_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Validation and derived constants
+// ---------------------------------------------------------------------------
+static bool fin(double v) { return std::isfinite(v); }
+
+// Largest countdown an exponential variate can produce: E = -ln(1 - phi) <= 32 ln 2.
+static constexpr double E_MAX = 22.18070977791825;
+
+static int validate(const bm_model *m, const bm_run *r)
+{
+    if (!m || !r) return fail(BM_ERR_INVALID_ARG, "model and run must not be NULL");
+    if (m->size != sizeof(bm_model)) return fail(BM_ERR_INVALID_ARG, "bm_model.size mismatch");
+    if (r->size != sizeof(bm_run)) return fail(BM_ERR_INVALID_ARG, "bm_run.size mismatch");
+    if (m->dyn > BM_INERTIAL) return fail(BM_ERR_INVALID_ARG, "unknown dynamics %u", m->dyn);
+    if (m->pot > BM_POT_FREE) return fail(BM_ERR_INVALID_ARG, "unknown potential %u", m->pot);
+    if (m->noise & ~7u) return fail(BM_ERR_INVALID_ARG, "unknown noise bits 0x%x", m->noise);
+    if (r->prec > BM_F32) return fail(BM_ERR_INVALID_ARG, "unknown precision %u", r->prec);
+    if (m->dyn == BM_INERTIAL && !(fin(m->gamma) && m->gamma > 0))
+        return fail(BM_ERR_INVALID_ARG, "gamma must be finite and > 0");
+    if (!fin(m->drive_amp) || !fin(m->force)) return fail(BM_ERR_INVALID_ARG, "drive/force not finite");
+    double dt;
+    if (r->steps_per_period > 0) {
+        if (!(fin(m->drive_omega) && m->drive_omega > 0))
+            return fail(BM_ERR_INVALID_ARG, "drive_omega must be > 0 when steps_per_period > 0");
+        if (r->dt != 0.0) return fail(BM_ERR_INVALID_ARG, "dt must be 0 when steps_per_period > 0");
+        dt = (2.0 * M_PI / m->drive_omega) / (double)r->steps_per_period;
+    } else {
+        if (m->drive_amp != 0.0)
+            return fail(BM_ERR_INVALID_ARG, "a periodic drive needs steps_per_period > 0");
+        if (!(fin(r->dt) && r->dt > 0)) return fail(BM_ERR_INVALID_ARG, "dt must be finite and > 0");
+        dt = r->dt;
+    }
+    if (m->noise & BM_NOISE_GAUSS)
+        if (!(fin(m->D) && m->D >= 0)) return fail(BM_ERR_INVALID_ARG, "D must be finite and >= 0");
+    if (m->noise & BM_NOISE_POISSON) {
+        if (!(fin(m->shot_rate) && m->shot_rate > 0))
+            return fail(BM_ERR_INVALID_ARG, "shot_rate must be finite and > 0");
+        if (!(fin(m->shot_mean) && m->shot_mean >= 0))
+            return fail(BM_ERR_INVALID_ARG, "shot_mean must be finite and >= 0");
+        if (E_MAX / (m->shot_rate * dt) >= 2147483000.0)
+            return fail(BM_ERR_UNSUPPORTED, "shot_rate*dt too small: waiting times overflow int32");
+    }
+    if (m->noise & BM_NOISE_DICH) {
+        if (!(fin(m->dich_Fa) && fin(m->dich_Fb) && m->dich_Fa >= 0 && m->dich_Fb >= 0))
+            return fail(BM_ERR_INVALID_ARG, "dichotomous levels must be finite and >= 0");
+        if (!(fin(m->dich_mua) && fin(m->dich_mub) && m->dich_mua > 0 && m->dich_mub > 0))
+            return fail(BM_ERR_INVALID_ARG, "dichotomous rates must be finite and > 0");
+        if (E_MAX / (std::fmin(m->dich_mua, m->dich_mub) * dt) >= 2147483000.0)
+            return fail(BM_ERR_UNSUPPORTED, "dichotomous rate*dt too small: dwell overflows int32");
+    }
+    if (r->n_paths < 1 || r->n_paths > 0xFFFFFFFFull)
+        return fail(BM_ERR_INVALID_ARG, "n_paths must be in [1, 2^32 - 1]");
+    if (!(fin(r->x0_lo) && fin(r->x0_hi) && r->x0_lo <= r->x0_hi))
+        return fail(BM_ERR_INVALID_ARG, "need finite x0_lo <= x0_hi");
+    if (!(fin(r->v0_lo) && fin(r->v0_hi) && r->v0_lo <= r->v0_hi))
+        return fail(BM_ERR_INVALID_ARG, "need finite v0_lo <= v0_hi");
+    if (r->window_start > 0xFFFFFFFFull) return fail(BM_ERR_INVALID_ARG, "window_start >= 2^32");
+    return BM_OK;
+}
+
+static double step_of(const bm_model *m, const bm_run *r)
+{
+    return r->steps_per_period > 0 ? (2.0 * M_PI / m->drive_omega) / (double)r->steps_per_period
+                                   : r->dt;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout (structure of arrays, each 256-byte aligned)
+// ---------------------------------------------------------------------------
+struct Layout {
+    size_t x, w, v, xi, wi, sP, kP, sD, mD, d, vp, part, tab, total;
+};
+
+static size_t up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static Layout layout(const bm_model *m, const bm_run *r)
+{
+    const size_t N = r->n_paths;
+    const size_t rs = r->prec == BM_F32 ? 4 : 8;
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o += up(bytes); return at; };
+    L.x = take(N * rs);
+    L.w = take(N * 4);
+    L.v = take(N * rs);
+    L.xi = take(N * rs);
+    L.wi = take(N * 4);
+    L.sP = take(N * 4);
+    L.kP = take(N * 4);
+    L.sD = take(N * 4);
+    L.mD = take(N * 4);
+    L.d = take(N * 4);
+    L.vp = take(N * 8);
+    L.part = take(((N + 63) / 64) * sizeof(Partial));
+    L.tab = take((size_t)(r->steps_per_period ? r->steps_per_period : 1) * rs);
+    L.total = o;
+    (void)m;
+    return L;
+}
+
+extern "C" int bm_ensemble_workspace_size(const bm_model *model, const bm_run *run, size_t *bytes)
+{
+    int rc = validate(model, run);
+    if (rc) return rc;
+    if (!bytes) return fail(BM_ERR_INVALID_ARG, "bytes must not be NULL");
+    *bytes = layout(model, run).total;
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Device check: the kernels are built for gfx950 only.
+// ---------------------------------------------------------------------------
+static int check_device(int *dev_out)
+{
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) return fail(BM_ERR_DEVICE, "no HIP device available");
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(BM_ERR_DEVICE, "device %d is %s; libbmotor is built for gfx950 only", dev,
+                    prop.gcnArchName);
+    *dev_out = dev;
+    return BM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Ensemble handle
+// ---------------------------------------------------------------------------
+struct bm_ensemble {
+    bm_model model;
+    bm_run run;
+    Layout lay;
+    char *ws;
+    hipStream_t stream;
+    KArgs k;                 // template of the kernel arguments
+    uint64_t n_done;
+    uint32_t ppl, block;
+    std::vector<double> tab64;
+    std::vector<float> tab32;
+};
+
+static void fill_kargs(bm_ensemble *e)
+{
+    const bm_model *m = &e->model;
+    const bm_run *r = &e->run;
+    KArgs &k = e->k;
+    std::memset(&k, 0, sizeof k);
+    char *b = e->ws;
+    const Layout &L = e->lay;
+    k.x = b + L.x; k.w = (int32_t *)(b + L.w); k.v = b + L.v; k.xi = b + L.xi;
+    k.wi = (int32_t *)(b + L.wi);
+    k.sP = (int32_t *)(b + L.sP); k.kP = (uint32_t *)(b + L.kP);
+    k.sD = (int32_t *)(b + L.sD); k.mD = (uint32_t *)(b + L.mD); k.d = (int32_t *)(b + L.d);
+    k.vp = (double *)(b + L.vp);
+    k.part = (Partial *)(b + L.part);
+    k.tab = b + L.tab;
+    k.n_paths = r->n_paths;
+    k.n_window = r->window_start;
+    k.spp = r->steps_per_period;
+    k.point = r->point_id;
+    k.key0 = (uint32_t)r->seed;
+    k.key1 = (uint32_t)(r->seed >> 32);
+    const double h = step_of(m, r);
+    k.dt = h;
+    k.gamma = m->dyn == BM_INERTIAL ? m->gamma : 0.0;
+    k.F = m->force;
+    k.L = m->pot == BM_POT_TENT ? 2.0 : 1.0;
+    if (m->noise & BM_NOISE_GAUSS) {
+        const double G = m->dyn == BM_INERTIAL ? std::sqrt(2.0 * m->gamma * m->D) : std::sqrt(2.0 * m->D);
+        k.g3 = G * std::sqrt(3.0 * h);
+    }
+    if (m->noise & BM_NOISE_POISSON) {
+        k.bias = m->shot_rate * m->shot_mean;
+        k.lam_dt = m->shot_rate * h;
+        k.zeta = m->shot_mean;
+    }
+    if (m->noise & BM_NOISE_DICH) {
+        k.Fa = m->dich_Fa;
+        k.Fb = m->dich_Fb;
+        k.mua_dt = m->dich_mua * h;
+        k.mub_dt = m->dich_mub * h;
+        k.p_hi = m->dich_mua / (m->dich_mua + m->dich_mub);
+    }
+    k.x0_lo = r->x0_lo; k.x0_w = r->x0_hi - r->x0_lo;
+    k.v0_lo = r->v0_lo; k.v0_w = r->v0_hi - r->v0_lo;
+}
+
+// drive + tilt table: a cos(2 pi k / spp) + F, k = 0 .. spp-1, evaluated in FP64
+static void fill_table(bm_ensemble *e)
+{
+    const uint32_t spp = e->run.steps_per_period;
+    e->tab64.assign(spp ? spp : 1, e->model.force);
+    for (uint32_t j = 0; j < spp; ++j)
+        e->tab64[j] = e->model.drive_amp * std::cos(2.0 * M_PI * (double)j / (double)spp) + e->model.force;
+    e->tab32.assign(e->tab64.begin(), e->tab64.end());
+}
+
+extern "C" int bm_ensemble_create(const bm_model *model, const bm_run *run, void *d_ws,
+                                  size_t ws_bytes, void *stream, bm_ensemble **out)
+{
+    int rc = validate(model, run);
+    if (rc) return rc;
+    if (!out) return fail(BM_ERR_INVALID_ARG, "out must not be NULL");
+    const Layout L = layout(model, run);
+    if (!d_ws || ((uintptr_t)d_ws & 255u)) return fail(BM_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    if (ws_bytes < L.total) return fail(BM_ERR_WORKSPACE, "workspace %zu B < %zu B needed", ws_bytes, L.total);
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+
+    bm_ensemble *e = new (std::nothrow) bm_ensemble();
+    if (!e) return fail(BM_ERR_INVALID_ARG, "out of host memory");
+    e->model = *model;
+    e->run = *run;
+    e->lay = L;
+    e->ws = (char *)d_ws;
+    e->stream = (hipStream_t)stream;
+    e->n_done = 0;
+    e->ppl = 1;
+    e->block = 256;
+    fill_kargs(e);
+    fill_table(e);
+
+    const bool f32 = run->prec == BM_F32;
+    const void *src = f32 ? (const void *)e->tab32.data() : (const void *)e->tab64.data();
+    const size_t tb = (f32 ? 4 : 8) * e->tab64.size();
+    // The table is read from host memory owned by the handle: wait for the copy so
+    // that the handle can be destroyed at any time after create returns.
+    hipError_t he = hipMemcpyAsync((char *)d_ws + L.tab, src, tb, hipMemcpyHostToDevice, e->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(e->stream);
+    if (he != hipSuccess) { delete e; return hip_fail(he, "drive table upload"); }
+
+    KArgs k = e->k;
+    k.snapshot = run->window_start == 0 ? 1u : 0u;
+    const int pot = (int)model->pot, noise = (int)model->noise;
+    if (f32)
+        he = model->dyn == BM_INERTIAL ? launch_init_f32_in(pot, noise, k, e->stream)
+                                       : launch_init_f32_od(pot, noise, k, e->stream);
+    else
+        he = model->dyn == BM_INERTIAL ? launch_init_f64_in(pot, noise, k, e->stream)
+                                       : launch_init_f64_od(pot, noise, k, e->stream);
+    if (he != hipSuccess) { delete e; return hip_fail(he, "init kernel launch"); }
+    *out = e;
+    return ok();
+}
+
+extern "C" int bm_ensemble_destroy(bm_ensemble *e)
+{
+    if (!e) return fail(BM_ERR_INVALID_ARG, "NULL handle");
+    delete e;
+    return ok();
+}
+
+extern "C" int bm_ensemble_set_tune(bm_ensemble *e, const bm_tune *t)
+{
+    if (!e) return fail(BM_ERR_INVALID_ARG, "NULL handle");
+    if (!t) { e->ppl = 1; e->block = 256; return ok(); }
+    if (t->size != sizeof(bm_tune)) return fail(BM_ERR_INVALID_ARG, "bm_tune.size mismatch");
+    if (t->paths_per_lane != 1 && t->paths_per_lane != 2)
+        return fail(BM_ERR_INVALID_ARG, "paths_per_lane must be 1 or 2");
+    if (t->paths_per_lane == 2 && e->run.prec != BM_F32)
+        return fail(BM_ERR_UNSUPPORTED, "paths_per_lane = 2 is built for FP32 paths only");
+    if (t->block != 64 && t->block != 128 && t->block != 256 && t->block != 512)
+        return fail(BM_ERR_INVALID_ARG, "block must be 64, 128, 256 or 512");
+    e->ppl = t->paths_per_lane;
+    e->block = t->block;
+    return ok();
+}
+
+extern "C" int bm_ensemble_steps(const bm_ensemble *e, uint64_t *n_done)
+{
+    if (!e || !n_done) return fail(BM_ERR_INVALID_ARG, "NULL argument");
+    *n_done = e->n_done;
+    return ok();
+}
+
+static hipError_t launch_advance(const bm_ensemble *e, const KArgs &k)
+{
+    const int pot = (int)e->model.pot, noise = (int)e->model.noise;
+    const int ppl = (int)e->ppl, blk = (int)e->block;
+    if (e->run.prec == BM_F32)
+        return e->model.dyn == BM_INERTIAL ? launch_advance_f32_in(pot, noise, ppl, blk, k, e->stream)
+                                           : launch_advance_f32_od(pot, noise, ppl, blk, k, e->stream);
+    return e->model.dyn == BM_INERTIAL ? launch_advance_f64_in(pot, noise, 1, blk, k, e->stream)
+                                       : launch_advance_f64_od(pot, noise, 1, blk, k, e->stream);
+}
+
+extern "C" int bm_integrate(bm_ensemble *e, uint64_t n_steps)
+{
+    if (!e) return fail(BM_ERR_INVALID_ARG, "NULL handle");
+    if (n_steps > 0xFFFFFFFFull - e->n_done)
+        return fail(BM_ERR_UNSUPPORTED, "total step count must stay below 2^32");
+    uint64_t n = e->n_done;
+    const uint64_t end = e->n_done + n_steps;
+    while (n < end) {
+        uint64_t stop = end;
+        const uint64_t nw = e->run.window_start;
+        if (n < nw && nw < stop) stop = nw;       // split so the snapshot falls on a launch end
+        KArgs k = e->k;
+        k.n0 = n;
+        k.n1 = stop;
+        k.snapshot = (stop == nw && nw > 0) ? 1u : 0u;
+        hipError_t he = launch_advance(e, k);
+        if (he != hipSuccess) return hip_fail(he, "integration kernel launch");
+        n = stop;
+        e->n_done = n;
+    }
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Reduction: chunk partials combined in a fixed order by one work-group.
+// ---------------------------------------------------------------------------
+__device__ static void finish_stats(DD s1, DD s2, uint64_t n, uint64_t bad, double tw, bm_stats *out)
+{
+    bm_stats st;
+    st.n = n;
+    st.n_nonfinite = bad;
+    st.t_window = tw;
+    const double nn = (double)n;
+    if (n == 0) {
+        st.mean = st.var = st.se = __builtin_nan("");
+    } else {
+        // mean = s1 / n as a double-double
+        const double mh = s1.hi / nn;
+        const double r = ((s1.hi - mh * nn) - fma(mh, nn, -(mh * nn))) + s1.lo;
+        const double ml = r / nn;
+        st.mean = mh + ml;
+        if (n < 2) {
+            st.var = st.se = __builtin_nan("");
+        } else {
+            // s2 - s1 * mean, with the product kept to double-double accuracy
+            const double p = s1.hi * mh;
+            const double pe = fma(s1.hi, mh, -p) + (s1.hi * ml + s1.lo * mh);
+            const DD num = dd_add(s2, DD{-p, -pe});
+            const double var = (num.hi + num.lo) / (nn - 1.0);
+            st.var = var;
+            st.se = sqrt(var / nn);
+        }
+    }
+    *out = st;
+}
+
+__global__ void __launch_bounds__(256) k_reduce_final(const Partial *part, uint64_t n_chunks, double tw,
+                                                      bm_stats *out)
+{
+    __shared__ double l1h[256], l1l[256], l2h[256], l2l[256];
+    __shared__ uint64_t lc[256], lb[256];
+    const uint32_t t = threadIdx.x;
+    const uint64_t lo = n_chunks * t / 256, hi = n_chunks * (t + 1) / 256;
+    DD s1{0.0, 0.0}, s2{0.0, 0.0};
+    uint64_t c = 0, b = 0;
+    for (uint64_t i = lo; i < hi; ++i) {
+        const Partial q = part[i];
+        s1 = dd_add(s1, DD{q.s1_hi, q.s1_lo});
+        s2 = dd_add(s2, DD{q.s2_hi, q.s2_lo});
+        c += q.n;
+        b += q.n_bad;
+    }
+    l1h[t] = s1.hi; l1l[t] = s1.lo; l2h[t] = s2.hi; l2l[t] = s2.lo; lc[t] = c; lb[t] = b;
+    __syncthreads();
+    for (uint32_t st = 128; st >= 1; st >>= 1) {
+        if (t < st) {
+            const DD a1{l1h[t], l1l[t]}, b1{l1h[t + st], l1l[t + st]};
+            const DD a2{l2h[t], l2l[t]}, b2{l2h[t + st], l2l[t + st]};
+            const DD r1 = dd_add(a1, b1), r2 = dd_add(a2, b2);
+            l1h[t] = r1.hi; l1l[t] = r1.lo; l2h[t] = r2.hi; l2l[t] = r2.lo;
+            lc[t] += lc[t + st];
+            lb[t] += lb[t + st];
+        }
+        __syncthreads();
+    }
+    if (t == 0) finish_stats(DD{l1h[0], l1l[0]}, DD{l2h[0], l2l[0]}, lc[0], lb[0], tw, out);
+}
+
+static void set_window(bm_ensemble *e, KArgs &k)
+{
+    k.t_window = (double)(e->n_done - e->run.window_start) * k.dt;
+}
+
+extern "C" int bm_reduce(bm_ensemble *e, bm_stats *d_out)
+{
+    if (!e) return fail(BM_ERR_INVALID_ARG, "NULL handle");
+    if (!d_out) return fail(BM_ERR_INVALID_ARG, "d_out must not be NULL");
+    if (e->n_done <= e->run.window_start)
+        return fail(BM_ERR_STATE, "window incomplete: %llu steps done, window starts at %llu",
+                    (unsigned long long)e->n_done, (unsigned long long)e->run.window_start);
+    KArgs k = e->k;
+    set_window(e, k);
+    const int pot = (int)e->model.pot;
+    hipError_t he = e->run.prec == BM_F32 ? launch_velocity_f32(pot, k, e->stream)
+                                          : launch_velocity_f64(pot, k, e->stream);
+    if (he != hipSuccess) return hip_fail(he, "velocity kernel launch");
+    const uint64_t chunks = (e->run.n_paths + 63) / 64;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, e->stream, k.part, chunks, k.t_window, d_out);
+    he = hipGetLastError();
+    if (he != hipSuccess) return hip_fail(he, "reduction kernel launch");
+    return ok();
+}
+
+extern "C" int bm_read_paths(bm_ensemble *e, uint64_t first, uint64_t count, double *d_x, double *d_v,
+                             int64_t *d_noise, double *d_vp)
+{
+    if (!e) return fail(BM_ERR_INVALID_ARG, "NULL handle");
+    if (first > e->run.n_paths || count > e->run.n_paths - first)
+        return fail(BM_ERR_INVALID_ARG, "path range [%llu, +%llu) outside the ensemble",
+                    (unsigned long long)first, (unsigned long long)count);
+    if (count == 0) return ok();
+    KArgs k = e->k;
+    k.n0 = first;
+    k.n1 = count;
+    const int with_vp = e->n_done > e->run.window_start ? 1 : 0;
+    if (with_vp) set_window(e, k);
+    const uint32_t noise = e->model.noise;
+    if (!(noise & BM_NOISE_POISSON)) { k.sP = nullptr; k.kP = nullptr; }
+    if (!(noise & BM_NOISE_DICH)) { k.sD = nullptr; k.mD = nullptr; k.d = nullptr; }
+    const int pot = (int)e->model.pot;
+    hipError_t he = e->run.prec == BM_F32
+                         ? launch_read_f32(pot, k, d_x, d_v, d_noise, d_vp, with_vp, e->stream)
+                         : launch_read_f64(pot, k, d_x, d_v, d_noise, d_vp, with_vp, e->stream);
+    if (he != hipSuccess) return hip_fail(he, "export kernel launch");
+    return ok();
+}

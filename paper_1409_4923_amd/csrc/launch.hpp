@@ -1,0 +1,28 @@
+// launch.hpp -- host-side launchers of the path kernels (one set per path
+// precision and dynamics, defined in paths_<prec>_<dyn>.hip).
+#pragma once
+
+#include "common.hpp"
+
+namespace bm {
+
+#define BM_DECLARE_LAUNCHERS(SUF)                                                                 \
+    hipError_t launch_init_##SUF(int pot, int noise, const KArgs &a, hipStream_t s);               \
+    hipError_t launch_advance_##SUF(int pot, int noise, int ppl, int block, const KArgs &a,       \
+                                    hipStream_t s);
+
+BM_DECLARE_LAUNCHERS(f32_od)
+BM_DECLARE_LAUNCHERS(f32_in)
+BM_DECLARE_LAUNCHERS(f64_od)
+BM_DECLARE_LAUNCHERS(f64_in)
+#undef BM_DECLARE_LAUNCHERS
+
+// per-path velocity + wave partials, and the state export (depend on precision and L only)
+hipError_t launch_velocity_f32(int pot, const KArgs &a, hipStream_t s);
+hipError_t launch_velocity_f64(int pot, const KArgs &a, hipStream_t s);
+hipError_t launch_read_f32(int pot, const KArgs &a, double *x, double *v, int64_t *nz, double *vp,
+                           int with_vp, hipStream_t s);
+hipError_t launch_read_f64(int pot, const KArgs &a, double *x, double *v, int64_t *nz, double *vp,
+                           int with_vp, hipStream_t s);
+
+} // namespace bm

@@ -1,0 +1,7 @@
+// Path kernels: float state, overdamped dynamics.
+#define BM_REAL float
+#define BM_DYN 0
+#define BM_SUF f32_od
+#define BM_MAX_PPL 2
+#define BM_WITH_EXPORT f32
+#include "paths_tu.inc"

@@ -1,0 +1,7 @@
+// Path kernels: double state, overdamped dynamics.
+#define BM_REAL double
+#define BM_DYN 0
+#define BM_SUF f64_od
+#define BM_MAX_PPL 1
+#define BM_WITH_EXPORT f64
+#include "paths_tu.inc"

@@ -1,0 +1,185 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, its structs match the header, and arguments are validated before any
+device call (with no device present, a valid create fails with BM_ERR_DEVICE)."""
+from __future__ import annotations
+
+import ctypes
+import glob
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_1409_4923_amd import bmotor as B
+from paper_1409_4923_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
+
+
+def declared_functions():
+    names = []
+    for h in HEADERS:
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names += re.findall(r"^[A-Za-z_][\w\s\*]*?\b(bm_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_headers_exist_and_declare_entry_points():
+    names = declared_functions()
+    for must in ("bm_ensemble_create", "bm_integrate", "bm_reduce", "bm_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (bm_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_binding_covers_every_declared_symbol():
+    assert set(declared_functions()) == {s[0] for s in B.SIGNATURES}
+
+
+def test_abi_version():
+    assert B.bm_abi_version() == 1
+
+
+_LAYOUT_C = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "bmotor.h"
+#define F(T, m) printf(#T " " #m " %zu\n", offsetof(T, m));
+int main(void) {
+  printf("bm_model size %zu\n", sizeof(bm_model));
+  printf("bm_run size %zu\n", sizeof(bm_run));
+  printf("bm_stats size %zu\n", sizeof(bm_stats));
+  printf("bm_tune size %zu\n", sizeof(bm_tune));
+  F(bm_model, gamma) F(bm_model, D) F(bm_model, dich_mub)
+  F(bm_run, dt) F(bm_run, n_steps) F(bm_run, seed) F(bm_run, v0_hi)
+  F(bm_stats, mean) F(bm_stats, t_window)
+  F(bm_tune, block)
+  return 0;
+}
+"""
+
+
+def test_struct_layout_matches_header():
+    with tempfile.TemporaryDirectory() as td:
+        src = os.path.join(td, "l.c")
+        exe = os.path.join(td, "l")
+        open(src, "w").write(_LAYOUT_C)
+        subprocess.check_call(["gcc", "-I" + os.path.join(ROOT, "include"), src, "-o", exe])
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    for line in out.strip().splitlines():
+        struct, field, val = line.split()
+        cls = getattr(B, struct)
+        if field == "size":
+            assert ctypes.sizeof(cls) == int(val), line
+        else:
+            assert getattr(cls, field).offset == int(val), line
+
+
+def _ok_model_run(**kw):
+    m, r = W.to_c(W.C1)
+    for k, v in kw.items():
+        setattr(m if hasattr(m, k) else r, k, v)
+    return m, r
+
+
+def _ws_rc(m, r):
+    n = ctypes.c_size_t()
+    return B.lib().bm_ensemble_workspace_size(ctypes.byref(m), ctypes.byref(r), ctypes.byref(n)), n.value
+
+
+def test_workspace_size_valid_configs():
+    for w in (W.C1, W.C2, W.C3):
+        m, r = W.to_c(w)
+        rc, n = _ws_rc(m, r)
+        assert rc == B.BM_OK, B.last_error()
+        assert n % 256 == 0
+        assert n >= w.n_paths * (4 * 8 + 8)          # the SoA state of every path
+    m, r = W.to_c(W.C2)
+    small = _ws_rc(m, r)[1]
+    r.n_paths *= 2
+    assert _ws_rc(m, r)[1] > small
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("size", 0, B.BM_ERR_INVALID_ARG),
+    ("dyn", 7, B.BM_ERR_INVALID_ARG),
+    ("pot", 9, B.BM_ERR_INVALID_ARG),
+    ("noise", 8, B.BM_ERR_INVALID_ARG),
+    ("prec", 3, B.BM_ERR_INVALID_ARG),
+    ("gamma", 0.0, B.BM_ERR_INVALID_ARG),
+    ("gamma", float("nan"), B.BM_ERR_INVALID_ARG),
+    ("drive_omega", 0.0, B.BM_ERR_INVALID_ARG),
+    ("dt", 0.1, B.BM_ERR_INVALID_ARG),             # dt must be 0 when spp > 0
+    ("D", -1.0, B.BM_ERR_INVALID_ARG),
+    ("n_paths", 0, B.BM_ERR_INVALID_ARG),
+    ("n_paths", 1 << 32, B.BM_ERR_INVALID_ARG),
+    ("x0_lo", 2.0, B.BM_ERR_INVALID_ARG),
+    ("force", float("inf"), B.BM_ERR_INVALID_ARG),
+])
+def test_invalid_arguments_rejected(field, value, code):
+    m, r = _ok_model_run()
+    setattr(m if field in dict(B.bm_model._fields_) and field != "size" else r, field, value)
+    rc, _ = _ws_rc(m, r)
+    assert rc == code, (field, value, rc, B.last_error())
+    assert B.last_error() != ""
+
+
+def test_drive_needs_steps_per_period():
+    m, r = _ok_model_run(steps_per_period=0, dt=0.01)
+    assert _ws_rc(m, r)[0] == B.BM_ERR_INVALID_ARG       # a = 4.2 without a phase grid
+    m.drive_amp = 0.0
+    assert _ws_rc(m, r)[0] == B.BM_OK
+
+
+def test_jump_rate_limits():
+    m, r = W.to_c(W.C2)
+    m.shot_rate = 0.0
+    assert _ws_rc(m, r)[0] == B.BM_ERR_INVALID_ARG
+    m.shot_rate = 1e-12                                   # waiting times overflow int32
+    assert _ws_rc(m, r)[0] == B.BM_ERR_UNSUPPORTED
+    m, r = W.to_c(W.C3)
+    m.dich_mua = -1.0
+    assert _ws_rc(m, r)[0] == B.BM_ERR_INVALID_ARG
+
+
+def test_null_arguments():
+    L = B.lib()
+    assert L.bm_ensemble_workspace_size(None, None, None) == B.BM_ERR_INVALID_ARG
+    assert L.bm_integrate(None, 10) == B.BM_ERR_INVALID_ARG
+    assert L.bm_reduce(None, None) == B.BM_ERR_INVALID_ARG
+    assert L.bm_ensemble_destroy(None) == B.BM_ERR_INVALID_ARG
+    assert L.bm_read_paths(None, 0, 1, None, None, None, None) == B.BM_ERR_INVALID_ARG
+    assert L.bm_ensemble_set_tune(None, None) == B.BM_ERR_INVALID_ARG
+
+
+def test_create_checks_workspace_then_device():
+    m, r = W.to_c(W.C1)
+    L = B.lib()
+    h = ctypes.c_void_p()
+    need = B.bm_ensemble_workspace_size(m, r)
+    # misaligned / too small workspace: rejected before touching the device
+    assert L.bm_ensemble_create(ctypes.byref(m), ctypes.byref(r), 0x1001, need, None,
+                                ctypes.byref(h)) == B.BM_ERR_WORKSPACE
+    assert L.bm_ensemble_create(ctypes.byref(m), ctypes.byref(r), 0x10000, need - 256, None,
+                                ctypes.byref(h)) == B.BM_ERR_WORKSPACE
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except Exception:
+        has_gpu = False
+    if not has_gpu:
+        rc = L.bm_ensemble_create(ctypes.byref(m), ctypes.byref(r), 0x10000, need, None, ctypes.byref(h))
+        assert rc == B.BM_ERR_DEVICE, B.last_error()
+        assert h.value is None
