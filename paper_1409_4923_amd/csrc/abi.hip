@@ -13,6 +13,7 @@
 #include "bmotor.h"
 #include "common.hpp"
 #include "launch.hpp"
+#include "paths.hpp"
 
 using namespace bm;
 
@@ -140,7 +141,7 @@ static Layout layout(const bm_model *m, const bm_run *r)
     L.d = take(N * 4);
     L.vp = take(N * 8);
     L.part = take(((N + 63) / 64) * sizeof(Partial));
-    L.tab = take((size_t)(r->steps_per_period ? r->steps_per_period : 1) * rs);
+    L.tab = take((size_t)((r->steps_per_period ? r->steps_per_period : 1) + 16) * rs);
     L.total = o;
     (void)m;
     return L;
@@ -209,14 +210,17 @@ static void fill_kargs(bm_ensemble *e)
     k.tab = b + L.tab;
     k.n_paths = r->n_paths;
     k.n_window = r->window_start;
-    k.spp = r->steps_per_period;
+    k.spp = r->steps_per_period ? r->steps_per_period : 1u;
     k.point = r->point_id;
     k.key0 = (uint32_t)r->seed;
     k.key1 = (uint32_t)(r->seed >> 32);
     const double h = step_of(m, r);
     k.dt = h;
     k.gamma = m->dyn == BM_INERTIAL ? m->gamma : 0.0;
-    k.F = m->force;
+    // constant-within-step forcing without a drive: tilt - Poisson bias + potential offset
+    const double bias = (m->noise & BM_NOISE_POISSON) ? m->shot_rate * m->shot_mean : 0.0;
+    const double pot_off = m->pot == BM_POT_RATCHET ? -M_PI : 0.0;
+    k.F = (m->force - bias) + pot_off;
     k.L = m->pot == BM_POT_TENT ? 2.0 : 1.0;
     if (m->noise & BM_NOISE_GAUSS) {
         const double G = m->dyn == BM_INERTIAL ? std::sqrt(2.0 * m->gamma * m->D) : std::sqrt(2.0 * m->D);
@@ -238,13 +242,18 @@ static void fill_kargs(bm_ensemble *e)
     k.v0_lo = r->v0_lo; k.v0_w = r->v0_hi - r->v0_lo;
 }
 
-// drive + tilt table: a cos(2 pi k / spp) + F, k = 0 .. spp-1, evaluated in FP64
+// Table of the constant-within-step forcing per drive phase, in FP64:
+// a cos(2 pi k / spp) + F - lambda zeta + potential offset, k = 0 .. spp-1.
+// Entries k >= period repeat entry k mod period (16 extra, one block of steps).
 static void fill_table(bm_ensemble *e)
 {
     const uint32_t spp = e->run.steps_per_period;
-    e->tab64.assign(spp ? spp : 1, e->model.force);
-    for (uint32_t j = 0; j < spp; ++j)
-        e->tab64[j] = e->model.drive_amp * std::cos(2.0 * M_PI * (double)j / (double)spp) + e->model.force;
+    const uint32_t per = spp ? spp : 1u;
+    e->tab64.assign(per + 16, e->k.F);
+    for (uint32_t j = 0; j < per + 16 && spp; ++j) {
+        const uint32_t i = j % spp;
+        e->tab64[j] = e->model.drive_amp * std::cos(2.0 * M_PI * (double)i / (double)spp) + e->k.F;
+    }
     e->tab32.assign(e->tab64.begin(), e->tab64.end());
 }
 
@@ -304,6 +313,16 @@ extern "C" int bm_ensemble_destroy(bm_ensemble *e)
     return ok();
 }
 
+// LDS of the jump queues of one work-group (see queue_bytes in paths_kernels.hpp).
+static size_t queue_lds_bytes(uint32_t noise, uint32_t prec, uint32_t ppl, uint32_t block)
+{
+    const size_t kick = prec == BM_F32 ? sizeof(KickEntry<float>) : sizeof(KickEntry<double>);
+    size_t per = 0;
+    if (noise & BM_NOISE_POISSON) per += (JCAP + 1) * kick;
+    if (noise & BM_NOISE_DICH) per += (JCAP + 1) * 4;
+    return per * ppl * block;
+}
+
 extern "C" int bm_ensemble_set_tune(bm_ensemble *e, const bm_tune *t)
 {
     if (!e) return fail(BM_ERR_INVALID_ARG, "NULL handle");
@@ -315,6 +334,9 @@ extern "C" int bm_ensemble_set_tune(bm_ensemble *e, const bm_tune *t)
         return fail(BM_ERR_UNSUPPORTED, "paths_per_lane = 2 is built for FP32 paths only");
     if (t->block != 64 && t->block != 128 && t->block != 256 && t->block != 512)
         return fail(BM_ERR_INVALID_ARG, "block must be 64, 128, 256 or 512");
+    if (queue_lds_bytes(e->model.noise, e->run.prec, t->paths_per_lane, t->block) > 65536)
+        return fail(BM_ERR_UNSUPPORTED, "jump queues of %u x %u lanes exceed 64 KiB of LDS",
+                    t->paths_per_lane, t->block);
     e->ppl = t->paths_per_lane;
     e->block = t->block;
     return ok();

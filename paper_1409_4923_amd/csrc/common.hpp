@@ -105,12 +105,12 @@ struct KArgs {
     int32_t *d;           // dichotomous state (0: -Fa, 1: +Fb)
     double *vp;           // per-path velocity, eq. (31)
     Partial *part;        // per-chunk partials
-    const void *tab;      // drive table a cos(2 pi k / spp) + F, k < spp (float/double)
+    const void *tab;      // forcing table, k < spp + 16 (float/double), see drive_at
 
     uint64_t n_paths;
     uint64_t n0, n1;      // step range of this launch
     uint64_t n_window;
-    uint32_t spp;         // 0: no periodic drive (constant force F)
+    uint32_t spp;         // period of the forcing table in steps (1: no periodic drive)
     uint32_t point;
     uint32_t key0, key1;
     uint32_t snapshot;    // store the window snapshot at the end of the launch

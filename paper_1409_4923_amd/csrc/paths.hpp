@@ -26,39 +26,49 @@ template <typename R> struct Path {
 };
 
 // ---------------------------------------------------------------------------
-// -V'(x)
+// -V'(x) + A, where A is the constant-within-step forcing of the step (drive,
+// tilt, Poisson bias, dichotomous level) plus the potential's constant offset
+// pot_offset<POT>() (folded into the drive table on the host).
 // ---------------------------------------------------------------------------
-template <int POT> __device__ __forceinline__ float force(float x)
+template <int POT> __device__ __forceinline__ float force_plus(float x, float A)
 {
+    constexpr float TWO_PI = 6.28318530717958648f;
     if constexpr (POT == POT_SIN) {
         // V = sin(2 pi x): -V' = -2 pi cos(2 pi x); v_cos_f32 takes its argument in turns
-        return -6.28318530717958648f * __builtin_amdgcn_cosf(x);
+        return __builtin_fmaf(-TWO_PI, __builtin_amdgcn_cosf(x), A);
     } else if constexpr (POT == POT_RATCHET) {
-        // V = -sin 2 pi x - sin(4 pi x)/4: -V' = 2 pi c + pi (2 c^2 - 1), c = cos 2 pi x
+        // V = -sin 2 pi x - sin(4 pi x)/4:  -V' = 2 pi c + pi (2 c^2 - 1) = c (2 pi c + 2 pi) - pi
         const float c = __builtin_amdgcn_cosf(x);
-        return 6.28318530717958648f * c + 3.14159265358979324f * (2.0f * c * c - 1.0f);
+        return __builtin_fmaf(c, __builtin_fmaf(TWO_PI, c, TWO_PI), A);   // A includes -pi
     } else if constexpr (POT == POT_TENT) {
         // eq. (2), period 2: +1 on [0, 1] (V = 1 - x), -1 on (1, 2) (V = 1 + x shifted)
         const float y = x - 2.0f * floorf(x * 0.5f);
-        return y <= 1.0f ? 1.0f : -1.0f;
+        return (y <= 1.0f ? 1.0f : -1.0f) + A;
     } else {
-        return 0.0f;
+        return A;
     }
 }
 
-template <int POT> __device__ __forceinline__ double force(double x)
+template <int POT> __device__ __forceinline__ double force_plus(double x, double A)
 {
     constexpr double PI = 3.14159265358979323846;
     if constexpr (POT == POT_SIN) {
-        return -2.0 * PI * cos(2.0 * PI * x);
+        return fma(-2.0 * PI, cos(2.0 * PI * x), A);
     } else if constexpr (POT == POT_RATCHET) {
-        return 2.0 * PI * cos(2.0 * PI * x) + PI * cos(4.0 * PI * x);
+        const double c = cos(2.0 * PI * x);
+        return fma(c, fma(2.0 * PI, c, 2.0 * PI), A);                     // A includes -pi
     } else if constexpr (POT == POT_TENT) {
         const double y = x - 2.0 * floor(x / 2.0);
-        return y <= 1.0 ? 1.0 : -1.0;
+        return (y <= 1.0 ? 1.0 : -1.0) + A;
     } else {
-        return 0.0;
+        return A;
     }
+}
+
+// Constant part of -V'(x) moved into the drive table.
+template <int POT> constexpr double pot_offset()
+{
+    return POT == POT_RATCHET ? -3.14159265358979323846 : 0.0;
 }
 
 template <int POT> constexpr double period() { return POT == POT_TENT ? 2.0 : 1.0; }
@@ -80,76 +90,135 @@ template <int POT, typename R> __device__ __forceinline__ void fold(Path<R> &s)
 }
 
 // ---------------------------------------------------------------------------
-// Algorithm 3 (white Poissonian noise): countdown on the dt grid; on expiry the
-// next waiting time s = floor(E_1 / (lambda dt)) and the amplitude z = zeta E_2.
-// Kick number k uses words (2(k%2), 2(k%2)+1) of block k/2.  FP64 decisions.
+// Jump processes on the dt grid.  The times and sizes of the jumps do not depend
+// on the path state, so each lane resolves all jumps of a window of JW steps in
+// one wave-uniform loop (the draws are the same as in Algorithms 3 / 4 step by
+// step) and queues them in LDS; the step loop then only compares the step
+// offset with the next queued offset.  A lane with more than JCAP jumps in a
+// window queues an "inline" marker and draws the rest at their steps.
 // ---------------------------------------------------------------------------
+constexpr uint32_t JW = 128;          // jump window, a multiple of 16 steps
+constexpr uint32_t JCAP = 8;          // queued jumps per lane and window
+constexpr uint32_t INLINE_BIT = 0x80000000u;
+
+template <typename R> struct KickEntry {
+    uint32_t off;   // step offset in the window (>= window length: none left)
+    R z;            // amplitude; < 0 marks "draw inline from here"
+};
+
+// Algorithm 3 draw for kick number k: next waiting time s (steps, FP64 decision)
+// and amplitude z = zeta E.  Kick k uses words (2(k%2), 2(k%2)+1) of block k/2.
 template <typename R>
-__device__ __forceinline__ R poisson_update(const KArgs &a, uint32_t path, Path<R> &s)
+__device__ __forceinline__ void kick_draw(const KArgs &a, uint32_t path, uint32_t k, uint32_t &s, R &z)
 {
-    R z = R(0);
-    if (s.sP <= 0) {
-        const U4 q = philox4x32_10(s.kP >> 1, path, a.point, TAG_POISSON, a.key0, a.key1);
-        const bool second = (s.kP & 1u) != 0u;
-        const uint32_t wa = second ? q.z : q.x;
-        const uint32_t wb = second ? q.w : q.y;
-        s.sP = (int32_t)floor(expo64(wa) / a.lam_dt);
-        z = (R)(a.zeta * expo64(wb));
-        s.kP += 1u;
-    } else {
-        s.sP -= 1;
+    const U4 q = philox4x32_10(k >> 1, path, a.point, TAG_POISSON, a.key0, a.key1);
+    const bool second = (k & 1u) != 0u;
+    s = (uint32_t)floor(expo64(second ? q.z : q.x) / a.lam_dt);
+    z = (R)(a.zeta * expo64(second ? q.w : q.y));
+}
+
+// Algorithm 4 draw for flip number m into state d_new: dwell s (steps, FP64).
+__device__ __forceinline__ uint32_t flip_draw(const KArgs &a, uint32_t path, uint32_t m, int32_t d_new)
+{
+    const U4 q = philox4x32_10(m >> 2, path, a.point, TAG_DICH, a.key0, a.key1);
+    const double mu_dt = d_new ? a.mub_dt : a.mua_dt;
+    return (uint32_t)floor(expo64(pick(q, m & 3u)) / mu_dt);
+}
+
+// Queue the kicks of one window.  `off` is the offset of the next kick (the
+// Algorithm 3 countdown at the window start).  q[slot * qs] is this lane's queue.
+template <typename R>
+__device__ __forceinline__ void kick_window(const KArgs &a, uint32_t path, uint32_t wlen, uint32_t off,
+                                            uint32_t &kP, KickEntry<R> *q, uint32_t qs)
+{
+    uint32_t slot = 0;
+    bool active = off < wlen;
+    while (__any(active)) {
+        if (active) {
+            if (slot < JCAP) {
+                uint32_t sn;
+                R z;
+                kick_draw<R>(a, path, kP, sn, z);
+                q[slot * qs] = KickEntry<R>{off, z};
+                ++slot;
+                ++kP;
+                off = off + 1u + sn;
+                active = off < wlen;
+            } else {
+                active = false;      // queue full: the rest of the window is drawn inline
+            }
+        }
     }
-    return z;
+    q[slot * qs] = KickEntry<R>{off, (slot == JCAP && off < wlen) ? R(-1) : R(0)};
+}
+
+// Queue the flips of one window; bit INLINE_BIT marks "draw inline from here".
+__device__ __forceinline__ void flip_window(const KArgs &a, uint32_t path, uint32_t wlen, uint32_t off,
+                                            uint32_t &mD, int32_t d, uint32_t *q, uint32_t qs)
+{
+    uint32_t slot = 0;
+    bool active = off < wlen;
+    while (__any(active)) {
+        if (active) {
+            if (slot < JCAP) {
+                d = 1 - d;
+                const uint32_t sn = flip_draw(a, path, mD, d);
+                q[slot * qs] = off;
+                ++slot;
+                ++mD;
+                off = off + 1u + sn;
+                active = off < wlen;
+            } else {
+                active = false;
+            }
+        }
+    }
+    q[slot * qs] = (slot == JCAP && off < wlen) ? (off | INLINE_BIT) : off;
 }
 
 // ---------------------------------------------------------------------------
-// Algorithm 4 (dichotomous noise): on expiry flip the state and draw the dwell
-// with the new state's leaving rate.  Flip m uses word m%4 of block m/4.
+// Algorithm 1: one predictor-corrector step.  A0 / A1 are the constant-within-
+// step forcing at t_n / t_{n+1} (drive, tilt, Poisson bias, dichotomous level:
+// part of the drift in all three evaluations); z is the Poisson kick, added once
+// in the corrector; hh = dt / 2.  With the FMA forms below one step costs three
+// cosines, twelve FMAs and seven adds (inertial).
 // ---------------------------------------------------------------------------
-template <typename R>
-__device__ __forceinline__ void dich_update(const KArgs &a, uint32_t path, Path<R> &s)
+template <int DYN, int POT, bool KICK, typename R>
+__device__ __forceinline__ void pc_step(Path<R> &s, R h, R hh, R ngam, R dxi, R z, R A0, R A1)
 {
-    if (s.sD <= 0) {
-        const U4 q = philox4x32_10(s.mD >> 2, path, a.point, TAG_DICH, a.key0, a.key1);
-        s.d = 1 - s.d;
-        const double mu_dt = s.d ? a.mub_dt : a.mua_dt;
-        s.sD = (int32_t)floor(expo64(pick(q, s.mD & 3u)) / mu_dt);
-        s.mD += 1u;
-    } else {
-        s.sD -= 1;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Algorithm 1: one predictor-corrector step.  A0 / A1 are the drive + tilt at
-// t_n / t_{n+1}; cst is the constant-within-step forcing (dichotomous level
-// minus the Poisson bias), part of the drift in all three evaluations; z is the
-// Poisson kick, added once in the corrector.
-// ---------------------------------------------------------------------------
-template <int DYN, int POT, typename R>
-__device__ __forceinline__ void pc_step(Path<R> &s, R h, R gam, R dxi, R z, R A0, R A1, R cst)
-{
-    const R half = R(0.5);
     if constexpr (DYN == DYN_INERTIAL) {
         const R x = s.x, v = s.v;
-        const R f1 = -gam * v + ((force<POT>(x) + A0) + cst);
-        const R xb = x + v * h;
-        const R vb = v + f1 * h + dxi;
-        R f2 = -gam * vb + ((force<POT>(xb) + A1) + cst);
-        const R xp = x + half * (v + vb) * h;                 // predictor
-        const R vpr = v + half * (f1 + f2) * h + dxi;
-        f2 = -gam * vpr + ((force<POT>(xp) + A1) + cst);
-        s.x = x + half * (v + vpr) * h;                      // corrector
-        s.v = v + half * (f1 + f2) * h + dxi + z;
+        const R f1 = fma(ngam, v, force_plus<POT>(x, A0));
+        const R xb = fma(v, h, x);
+        const R vb = fma(f1, h, v) + dxi;
+        const R f2 = fma(ngam, vb, force_plus<POT>(xb, A1));
+        const R xp = fma(v + vb, hh, x);                       // predictor
+        const R vpr = fma(f1 + f2, hh, v) + dxi;
+        const R f3 = fma(ngam, vpr, force_plus<POT>(xp, A1));
+        s.x = fma(v + vpr, hh, x);                             // corrector
+        R vn = fma(f1 + f3, hh, v) + dxi;
+        if constexpr (KICK) vn = vn + z;
+        s.v = vn;
     } else {
         const R x = s.x;
-        const R f1 = (force<POT>(x) + A0) + cst;
-        const R xb = x + f1 * h + dxi;
-        R f2 = (force<POT>(xb) + A1) + cst;
-        const R xp = x + half * (f1 + f2) * h + dxi;          // predictor
-        f2 = (force<POT>(xp) + A1) + cst;
-        s.x = x + half * (f1 + f2) * h + dxi + z;            // corrector
+        const R f1 = force_plus<POT>(x, A0);
+        const R xb = fma(f1, h, x) + dxi;
+        const R f2 = force_plus<POT>(xb, A1);
+        const R xp = fma(f1 + f2, hh, x) + dxi;                // predictor
+        const R f3 = force_plus<POT>(xp, A1);
+        R xn = fma(f1 + f3, hh, x) + dxi;                      // corrector
+        if constexpr (KICK) xn = xn + z;
+        s.x = xn;
     }
+}
+
+// u * 6 mod 2^32 with two full-rate shifts (the compiler would otherwise emit a
+// quarter-rate 32-bit multiply): the next base-6 digit of the fraction u / 2^32.
+__device__ __forceinline__ uint32_t times6(uint32_t u)
+{
+    uint32_t r;
+    asm("v_lshl_add_u32 %0, %1, 1, %1\n\tv_lshlrev_b32 %0, 1, %0" : "=v"(r) : "v"(u));
+    return r;
 }
 
 } // namespace bm

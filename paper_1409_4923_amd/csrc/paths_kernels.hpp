@@ -33,26 +33,69 @@ __device__ __forceinline__ void store_path(const KArgs &a, uint32_t p, const Pat
     if (a.snapshot) { arr<R>(a.xi)[p] = s.x; a.wi[p] = s.w; }
 }
 
-// Drive + tilt at phase k (0 <= k < spp), or the constant tilt without a drive.
+// Constant-within-step forcing at phase k: drive + tilt - Poisson bias + potential
+// offset, from the host-built table (period a.spp >= 1, extended by 16 entries so
+// that the 17 values of a 16-step block are contiguous).
 template <typename R> __device__ __forceinline__ R drive_at(const KArgs &a, uint32_t k)
 {
-    return a.spp ? reinterpret_cast<const R *>(a.tab)[k] : (R)a.F;
+    return reinterpret_cast<const R *>(a.tab)[k];
 }
 
-// One complete step n -> n+1 of one path: jump processes, then Algorithm 1, then
-// folding.  `dxi` is the Algorithm 2 increment for this step.
+// Per-lane cursor into the LDS jump queues of the current window.
+template <typename R> struct JumpCursor {
+    uint32_t nP;    // offset of the next kick in the window
+    R zP;           // its amplitude (< 0: kicks are drawn inline from nP on)
+    uint32_t cP;    // next queue slot
+    uint32_t nD;    // offset of the next flip
+    uint32_t cD;    // next queue slot (FLIP_INLINE: flips drawn inline)
+};
+constexpr uint32_t FLIP_INLINE = 0xFFFFFFFFu;
+
+// One step of one path at window offset `off`: jumps due at this step, then
+// Algorithm 1.  `dxi` is the Algorithm 2 increment.  (Folding is done by the caller.)
 template <typename R, int DYN, int POT, int NOISE>
-__device__ __forceinline__ void full_step(const KArgs &a, uint32_t path, Path<R> &s, R dxi, R h,
-                                          R gam, R A0, R A1, R bias, R Fa, R Fb)
+__device__ __forceinline__ void full_step(const KArgs &a, uint32_t path, Path<R> &s, JumpCursor<R> &J,
+                                          const KickEntry<R> *kq, const uint32_t *fq, uint32_t qs,
+                                          uint32_t off, R dxi, R h, R hh, R ngam, R A0, R A1, R Fa, R Fb)
 {
     R z = R(0);
-    if constexpr ((NOISE & NZ_POISSON) != 0) z = poisson_update<R>(a, path, s);
-    if constexpr ((NOISE & NZ_DICH) != 0) dich_update<R>(a, path, s);
-    R cst = R(0);
-    if constexpr ((NOISE & NZ_DICH) != 0) cst = s.d ? Fb : -Fa;
-    if constexpr ((NOISE & NZ_POISSON) != 0) cst = cst - bias;
-    pc_step<DYN, POT, R>(s, h, gam, dxi, z, A0, A1, cst);
-    fold<POT, R>(s);
+    if constexpr ((NOISE & NZ_POISSON) != 0) {
+        if (J.nP == off) {                       // Algorithm 3: s <= 0 at this step
+            if (J.zP >= R(0)) {
+                z = J.zP;
+                const KickEntry<R> e = kq[J.cP * qs];
+                ++J.cP;
+                J.nP = e.off;
+                J.zP = e.z;
+            } else {
+                uint32_t sn;
+                kick_draw<R>(a, path, s.kP, sn, z);
+                ++s.kP;
+                J.nP = off + 1u + sn;
+            }
+        }
+    }
+    if constexpr ((NOISE & NZ_DICH) != 0) {
+        if (J.nD == off) {                       // Algorithm 4: s <= 0 at this step
+            s.d = 1 - s.d;
+            if (J.cD != FLIP_INLINE) {
+                const uint32_t e = fq[J.cD * qs];
+                ++J.cD;
+                if (e & INLINE_BIT) J.cD = FLIP_INLINE;
+                J.nD = e & ~INLINE_BIT;
+            } else {
+                const uint32_t sn = flip_draw(a, path, s.mD, s.d);
+                ++s.mD;
+                J.nD = off + 1u + sn;
+            }
+        }
+    }
+    if constexpr ((NOISE & NZ_DICH) != 0) {
+        const R lev = s.d ? Fb : -Fa;
+        A0 = A0 + lev;
+        A1 = A1 + lev;
+    }
+    pc_step<DYN, POT, (NOISE & NZ_POISSON) != 0, R>(s, h, hh, ngam, dxi, z, A0, A1);
 }
 
 template <typename R>
@@ -61,19 +104,35 @@ __device__ __forceinline__ R three_point(uint32_t u, R g3)
     return u < T_MINUS ? -g3 : (u < T_PLUS ? g3 : R(0));
 }
 
+// LDS bytes of the jump queues per lane and path.
+template <typename R, int NOISE> constexpr uint32_t queue_bytes()
+{
+    return (((NOISE & NZ_POISSON) != 0) ? (JCAP + 1) * (uint32_t)sizeof(KickEntry<R>) : 0u) +
+           (((NOISE & NZ_DICH) != 0) ? (JCAP + 1) * 4u : 0u);
+}
+
 // ---------------------------------------------------------------------------
-// Integration kernel: advances paths over steps [n0, n1).  Steps are grouped in
-// blocks of 16 sharing one Philox call for Algorithm 2 (4 words x 4 base-6
-// digits).  Lane layout: path = (blockIdx.x * PPL + j) * blockDim.x + threadIdx.x.
+// Integration kernel: advances paths over steps [n0, n1) in windows of JW steps
+// (aligned to multiples of JW).  Per window the jumps are queued, then the steps
+// run in blocks of 16 sharing one Philox call for Algorithm 2 (4 words x 4
+// base-6 digits).  Lane layout: path = (blockIdx.x * PPL + j) * blockDim.x + tid.
+// Dynamic LDS: the jump queues, slot-major (slot * PPL * blockDim + column).
 // ---------------------------------------------------------------------------
 template <typename R, int DYN, int POT, int NOISE, int PPL>
 __global__ void __launch_bounds__(512) k_advance(const KArgs a)
 {
+    extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t base = blockIdx.x * PPL * blockDim.x + threadIdx.x;
     if ((uint64_t)base >= a.n_paths) return;
+    const uint32_t qs = PPL * blockDim.x;
+    KickEntry<R> *kq = reinterpret_cast<KickEntry<R> *>(smem);
+    uint32_t *fq = reinterpret_cast<uint32_t *>(
+        smem + (((NOISE & NZ_POISSON) != 0) ? (JCAP + 1) * qs * sizeof(KickEntry<R>) : 0));
+
     uint32_t path[PPL];
     bool valid[PPL];
     Path<R> s[PPL];
+    JumpCursor<R> J[PPL];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
         const uint64_t p = (uint64_t)base + (uint64_t)j * blockDim.x;
@@ -81,70 +140,111 @@ __global__ void __launch_bounds__(512) k_advance(const KArgs a)
         path[j] = valid[j] ? (uint32_t)p : base;
         load_path<R, POT, NOISE>(a, path[j], s[j]);
     }
-    const R h = (R)a.dt, gam = (R)a.gamma, g3 = (R)a.g3;
-    const R bias = (R)a.bias, Fa = (R)a.Fa, Fb = (R)a.Fb;
+    const R h = (R)a.dt, hh = (R)(0.5 * a.dt), ngam = (R)(-a.gamma), g3 = (R)a.g3;
+    const R Fa = (R)a.Fa, Fb = (R)a.Fb;
 
     uint64_t n = a.n0;
-    uint32_t k = a.spp ? (uint32_t)(n % a.spp) : 0u;
-    R A0 = drive_at<R>(a, k);
+    uint32_t k = (uint32_t)(n % a.spp);           // drive phase of step n
 
-    // Generic single step (used at block-unaligned starts and ends).
-    auto one_step = [&](uint64_t nn) {
-        const uint32_t k1 = (a.spp && k + 1u == a.spp) ? 0u : k + 1u;
-        const R A1 = drive_at<R>(a, a.spp ? k1 : 0u);
+    auto col = [&](int j) { return (uint32_t)j * blockDim.x + threadIdx.x; };
+
+    while (n < a.n1) {
+        const uint64_t wend = ((n / JW) + 1u) * JW < a.n1 ? ((n / JW) + 1u) * JW : a.n1;
+        const uint32_t wlen = (uint32_t)(wend - n);
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-            R dxi = R(0);
-            if constexpr ((NOISE & NZ_GAUSS) != 0) {
-                const U4 q = philox4x32_10((uint32_t)(nn >> 4), path[j], a.point, TAG_GAUSS,
-                                           a.key0, a.key1);
-                uint32_t u = pick(q, (uint32_t)(nn >> 2) & 3u);
-                for (uint32_t t = 0; t < (uint32_t)(nn & 3u); ++t) u *= 6u;
-                dxi = three_point<R>(u, g3);
+            if constexpr ((NOISE & NZ_POISSON) != 0) {
+                kick_window<R>(a, path[j], wlen, (uint32_t)s[j].sP, s[j].kP, kq + col(j), qs);
+                const KickEntry<R> e = kq[col(j)];
+                J[j].nP = e.off;
+                J[j].zP = e.z;
+                J[j].cP = 1u;
             }
-            full_step<R, DYN, POT, NOISE>(a, path[j], s[j], dxi, h, gam, A0, A1, bias, Fa, Fb);
+            if constexpr ((NOISE & NZ_DICH) != 0) {
+                flip_window(a, path[j], wlen, (uint32_t)s[j].sD, s[j].mD, s[j].d, fq + col(j), qs);
+                const uint32_t e = fq[col(j)];
+                J[j].nD = e & ~INLINE_BIT;
+                J[j].cD = (e & INLINE_BIT) ? FLIP_INLINE : 1u;
+            }
         }
-        k = k1;
-        A0 = A1;
-    };
+        uint32_t off = 0;
 
-    while (n < a.n1 && (n & 15u) != 0u) { one_step(n); ++n; }
-
-    while (n + 16u <= a.n1) {
-        U4 q[PPL];
+        // Generic single step (block-unaligned window heads and tails).
+        auto one_step = [&]() {
+            const R A0 = drive_at<R>(a, k);
+            const R A1 = drive_at<R>(a, k + 1u);
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) {
-            if constexpr ((NOISE & NZ_GAUSS) != 0)
-                q[j] = philox4x32_10((uint32_t)(n >> 4), path[j], a.point, TAG_GAUSS, a.key0, a.key1);
-            else
-                q[j] = U4{0u, 0u, 0u, 0u};
-        }
-#pragma unroll
-        for (int wd = 0; wd < 4; ++wd) {
-            uint32_t u[PPL];
-#pragma unroll
-            for (int j = 0; j < PPL; ++j) u[j] = pick(q[j], (uint32_t)wd);
-#pragma unroll
-            for (int dg = 0; dg < 4; ++dg) {
-                const uint32_t k1 = (a.spp && k + 1u == a.spp) ? 0u : k + 1u;
-                const R A1 = drive_at<R>(a, a.spp ? k1 : 0u);
-#pragma unroll
-                for (int j = 0; j < PPL; ++j) {
-                    R dxi = R(0);
-                    if constexpr ((NOISE & NZ_GAUSS) != 0) {
-                        dxi = three_point<R>(u[j], g3);
-                        u[j] *= 6u;   // next base-6 digit
-                    }
-                    full_step<R, DYN, POT, NOISE>(a, path[j], s[j], dxi, h, gam, A0, A1, bias, Fa, Fb);
+            for (int j = 0; j < PPL; ++j) {
+                R dxi = R(0);
+                if constexpr ((NOISE & NZ_GAUSS) != 0) {
+                    const U4 q = philox4x32_10((uint32_t)(n >> 4), path[j], a.point, TAG_GAUSS,
+                                               a.key0, a.key1);
+                    uint32_t u = pick(q, (uint32_t)(n >> 2) & 3u);
+                    for (uint32_t t = 0; t < (uint32_t)(n & 3u); ++t) u = times6(u);
+                    dxi = three_point<R>(u, g3);
                 }
-                k = k1;
-                A0 = A1;
+                full_step<R, DYN, POT, NOISE>(a, path[j], s[j], J[j], kq + col(j), fq + col(j), qs, off,
+                                              dxi, h, hh, ngam, A0, A1, Fa, Fb);
             }
-        }
-        n += 16u;
-    }
+            k = (k + 1u == a.spp) ? 0u : k + 1u;
+            ++n;
+            ++off;
+            if ((n & 15u) == 0u) {                   // fold at absolute multiples of 16 steps
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) fold<POT, R>(s[j]);
+            }
+        };
 
-    while (n < a.n1) { one_step(n); ++n; }
+        while (n < wend && (n & 15u) != 0u) one_step();
+
+        while (n + 16u <= wend) {
+            U4 q[PPL];
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                if constexpr ((NOISE & NZ_GAUSS) != 0)
+                    q[j] = philox4x32_10((uint32_t)(n >> 4), path[j], a.point, TAG_GAUSS, a.key0, a.key1);
+                else
+                    q[j] = U4{0u, 0u, 0u, 0u};
+            }
+            R A[17];                                  // forcing at steps n .. n+16
+#pragma unroll
+            for (int t = 0; t < 17; ++t) A[t] = drive_at<R>(a, k + (uint32_t)t);
+#pragma unroll
+            for (int wd = 0; wd < 4; ++wd) {
+                uint32_t u[PPL];
+#pragma unroll
+                for (int j = 0; j < PPL; ++j) u[j] = pick(q[j], (uint32_t)wd);
+#pragma unroll
+                for (int dg = 0; dg < 4; ++dg) {
+                    const R A0 = A[4 * wd + dg], A1 = A[4 * wd + dg + 1];
+#pragma unroll
+                    for (int j = 0; j < PPL; ++j) {
+                        R dxi = R(0);
+                        if constexpr ((NOISE & NZ_GAUSS) != 0) {
+                            dxi = three_point<R>(u[j], g3);
+                            u[j] = times6(u[j]);   // next base-6 digit
+                        }
+                        full_step<R, DYN, POT, NOISE>(a, path[j], s[j], J[j], kq + col(j), fq + col(j), qs,
+                                                      off, dxi, h, hh, ngam, A0, A1, Fa, Fb);
+                    }
+                    ++off;
+                }
+            }
+            n += 16u;
+            k = (k + 16u) % a.spp;
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) fold<POT, R>(s[j]);   // x mod L at the block end
+        }
+
+        while (n < wend) one_step();
+
+        // Countdowns at the window end: the next jump lies at or beyond it.
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            if constexpr ((NOISE & NZ_POISSON) != 0) s[j].sP = (int32_t)(J[j].nP - wlen);
+            if constexpr ((NOISE & NZ_DICH) != 0) s[j].sD = (int32_t)(J[j].nD - wlen);
+        }
+    }
 
 #pragma unroll
     for (int j = 0; j < PPL; ++j)
