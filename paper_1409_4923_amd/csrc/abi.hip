@@ -113,6 +113,9 @@ static double step_of(const bm_model *m, const bm_run *r)
                                    : r->dt;
 }
 
+// Entries of the forcing table: one drive period plus one block of 16 steps.
+static size_t table_entries(const bm_run *r) { return (r->steps_per_period ? r->steps_per_period : 1u) + 16; }
+
 // ---------------------------------------------------------------------------
 // Workspace layout (structure of arrays, each 256-byte aligned)
 // ---------------------------------------------------------------------------
@@ -141,7 +144,7 @@ static Layout layout(const bm_model *m, const bm_run *r)
     L.d = take(N * 4);
     L.vp = take(N * 8);
     L.part = take(((N + 63) / 64) * sizeof(Partial));
-    L.tab = take((size_t)((r->steps_per_period ? r->steps_per_period : 1) + 16) * rs);
+    L.tab = take(table_entries(r) * rs);
     L.total = o;
     (void)m;
     return L;
@@ -193,10 +196,79 @@ struct bm_ensemble {
     std::vector<float> tab32;
 };
 
+// Constant part of the forcing without a drive: tilt - Poisson bias + potential offset.
+static double forcing_constant(const bm_model *m)
+{
+    const double bias = (m->noise & BM_NOISE_POISSON) ? m->shot_rate * m->shot_mean : 0.0;
+    const double pot_off = m->pot == BM_POT_RATCHET ? -M_PI : 0.0;
+    return (m->force - bias) + pot_off;
+}
+
+// Table of the constant-within-step forcing per drive phase, in FP64:
+// a cos(2 pi k / spp) + F - lambda zeta + potential offset, k = 0 .. spp-1,
+// followed by 16 entries repeating the start (one block of steps).
+static void forcing_table(const bm_model *m, const bm_run *r, std::vector<double> &tab)
+{
+    const uint32_t spp = r->steps_per_period;
+    const uint32_t per = spp ? spp : 1u;
+    const double c = forcing_constant(m);
+    tab.assign(per + 16, c);
+    for (uint32_t j = 0; j < per + 16 && spp; ++j) {
+        const uint32_t i = j % spp;
+        tab[j] = m->drive_amp * std::cos(2.0 * M_PI * (double)i / (double)spp) + c;
+    }
+}
+
+
+// Per-point constants shared by the ensemble and scan kernels.
+static PointConst point_const(const bm_model *m, const bm_run *r, const void *d_tab)
+{
+    PointConst k;
+    std::memset(&k, 0, sizeof k);
+    k.tab = d_tab;
+    k.n_paths = (uint32_t)r->n_paths;
+    k.n_steps = r->n_steps;
+    k.n_window = r->window_start;
+    k.spp = r->steps_per_period ? r->steps_per_period : 1u;
+    k.point = r->point_id;
+    k.key0 = (uint32_t)r->seed;
+    k.key1 = (uint32_t)(r->seed >> 32);
+    const double h = step_of(m, r);
+    k.dt = h;
+    k.gamma = m->dyn == BM_INERTIAL ? m->gamma : 0.0;
+    if (m->noise & BM_NOISE_GAUSS) {
+        const double G = m->dyn == BM_INERTIAL ? std::sqrt(2.0 * m->gamma * m->D) : std::sqrt(2.0 * m->D);
+        k.g3 = G * std::sqrt(3.0 * h);
+    }
+    // FP32 countdown estimates: error < 3e-7 / (rate dt) + 4.2e-7 X (rounding of
+    // 1 - phi, v_log_f32 near 1, the scale); the tolerance is about 7x / 10x that.
+    const double LN2 = 0.69314718055994530942;
+    k.tol1 = 4e-6f;
+    if (m->noise & BM_NOISE_POISSON) {
+        k.lam_dt = m->shot_rate * h;
+        k.zeta = m->shot_mean;
+        k.c_lam = (float)(LN2 / k.lam_dt);
+        k.tol0_lam = (float)(2e-6 / k.lam_dt + 1e-6);
+        k.zeta_ln2 = (float)(-m->shot_mean * LN2);
+    }
+    if (m->noise & BM_NOISE_DICH) {
+        k.Fa = m->dich_Fa;
+        k.Fb = m->dich_Fb;
+        k.mua_dt = m->dich_mua * h;
+        k.mub_dt = m->dich_mub * h;
+        k.p_hi = m->dich_mua / (m->dich_mua + m->dich_mub);
+        k.c_mua = (float)(LN2 / k.mua_dt);
+        k.c_mub = (float)(LN2 / k.mub_dt);
+        k.tol0_mua = (float)(2e-6 / k.mua_dt + 1e-6);
+        k.tol0_mub = (float)(2e-6 / k.mub_dt + 1e-6);
+    }
+    k.x0_lo = r->x0_lo; k.x0_w = r->x0_hi - r->x0_lo;
+    k.v0_lo = r->v0_lo; k.v0_w = r->v0_hi - r->v0_lo;
+    return k;
+}
+
 static void fill_kargs(bm_ensemble *e)
 {
-    const bm_model *m = &e->model;
-    const bm_run *r = &e->run;
     KArgs &k = e->k;
     std::memset(&k, 0, sizeof k);
     char *b = e->ws;
@@ -207,53 +279,12 @@ static void fill_kargs(bm_ensemble *e)
     k.sD = (int32_t *)(b + L.sD); k.mD = (uint32_t *)(b + L.mD); k.d = (int32_t *)(b + L.d);
     k.vp = (double *)(b + L.vp);
     k.part = (Partial *)(b + L.part);
-    k.tab = b + L.tab;
-    k.n_paths = r->n_paths;
-    k.n_window = r->window_start;
-    k.spp = r->steps_per_period ? r->steps_per_period : 1u;
-    k.point = r->point_id;
-    k.key0 = (uint32_t)r->seed;
-    k.key1 = (uint32_t)(r->seed >> 32);
-    const double h = step_of(m, r);
-    k.dt = h;
-    k.gamma = m->dyn == BM_INERTIAL ? m->gamma : 0.0;
-    // constant-within-step forcing without a drive: tilt - Poisson bias + potential offset
-    const double bias = (m->noise & BM_NOISE_POISSON) ? m->shot_rate * m->shot_mean : 0.0;
-    const double pot_off = m->pot == BM_POT_RATCHET ? -M_PI : 0.0;
-    k.F = (m->force - bias) + pot_off;
-    k.L = m->pot == BM_POT_TENT ? 2.0 : 1.0;
-    if (m->noise & BM_NOISE_GAUSS) {
-        const double G = m->dyn == BM_INERTIAL ? std::sqrt(2.0 * m->gamma * m->D) : std::sqrt(2.0 * m->D);
-        k.g3 = G * std::sqrt(3.0 * h);
-    }
-    if (m->noise & BM_NOISE_POISSON) {
-        k.bias = m->shot_rate * m->shot_mean;
-        k.lam_dt = m->shot_rate * h;
-        k.zeta = m->shot_mean;
-    }
-    if (m->noise & BM_NOISE_DICH) {
-        k.Fa = m->dich_Fa;
-        k.Fb = m->dich_Fb;
-        k.mua_dt = m->dich_mua * h;
-        k.mub_dt = m->dich_mub * h;
-        k.p_hi = m->dich_mua / (m->dich_mua + m->dich_mub);
-    }
-    k.x0_lo = r->x0_lo; k.x0_w = r->x0_hi - r->x0_lo;
-    k.v0_lo = r->v0_lo; k.v0_w = r->v0_hi - r->v0_lo;
+    k.p = point_const(&e->model, &e->run, b + L.tab);
 }
 
-// Table of the constant-within-step forcing per drive phase, in FP64:
-// a cos(2 pi k / spp) + F - lambda zeta + potential offset, k = 0 .. spp-1.
-// Entries k >= period repeat entry k mod period (16 extra, one block of steps).
 static void fill_table(bm_ensemble *e)
 {
-    const uint32_t spp = e->run.steps_per_period;
-    const uint32_t per = spp ? spp : 1u;
-    e->tab64.assign(per + 16, e->k.F);
-    for (uint32_t j = 0; j < per + 16 && spp; ++j) {
-        const uint32_t i = j % spp;
-        e->tab64[j] = e->model.drive_amp * std::cos(2.0 * M_PI * (double)i / (double)spp) + e->k.F;
-    }
+    forcing_table(&e->model, &e->run, e->tab64);
     e->tab32.assign(e->tab64.begin(), e->tab64.end());
 }
 
@@ -450,7 +481,7 @@ __global__ void __launch_bounds__(256) k_reduce_final(const Partial *part, uint6
 
 static void set_window(bm_ensemble *e, KArgs &k)
 {
-    k.t_window = (double)(e->n_done - e->run.window_start) * k.dt;
+    k.t_window = (double)(e->n_done - e->run.window_start) * k.p.dt;
 }
 
 extern "C" int bm_reduce(bm_ensemble *e, bm_stats *d_out)

@@ -90,10 +90,38 @@ struct Partial {
 };
 
 // ---------------------------------------------------------------------------
-// Kernel arguments (passed by value).  Arrays are structure-of-arrays over paths.
+// Constants of one parameter point (one ensemble, or one point of a scan).
+// ---------------------------------------------------------------------------
+struct PointConst {
+    const void *tab;      // forcing table, k < spp + 16 (float/double), see drive_at
+    uint32_t spp;         // period of the forcing table in steps (1: no periodic drive)
+    uint32_t point;       // point index in the random-stream counter
+    uint32_t key0, key1;  // Philox key (seed)
+    uint32_t n_paths;
+    uint32_t pad;
+    uint64_t n_steps;     // horizon (scan)
+    uint64_t n_window;    // eq. (31): step index of t_i
+    double dt, gamma;
+    double g3;            // G sqrt(3 dt)
+    double lam_dt;        // lambda dt
+    double zeta;
+    double Fa, Fb;
+    double mua_dt, mub_dt;
+    double p_hi;          // stationary Pr{+Fb} = mu_a / (mu_a + mu_b)
+    double x0_lo, x0_w, v0_lo, v0_w;
+    // FP32 estimates of the countdown X = E / (rate dt): X ~= -log2(1 - phi) * c,
+    // trusted when its fraction is farther than tol0 + tol1 X from an integer.
+    float c_lam, c_mua, c_mub;   // ln 2 / (rate dt)
+    float tol0_lam, tol0_mua, tol0_mub, tol1;
+    float zeta_ln2;              // -zeta ln 2: z = zeta E = log2(1 - phi) * zeta_ln2
+};
+
+// ---------------------------------------------------------------------------
+// Kernel arguments of the ensemble kernels (passed by value).  Arrays are
+// structure-of-arrays over paths.
 // ---------------------------------------------------------------------------
 struct KArgs {
-    void *x;              // folded position [0, L): float or double
+    void *x;              // folded position: float or double
     int32_t *w;           // folded periods
     void *v;              // velocity (inertial): float or double
     void *xi;             // position at the window start
@@ -105,25 +133,10 @@ struct KArgs {
     int32_t *d;           // dichotomous state (0: -Fa, 1: +Fb)
     double *vp;           // per-path velocity, eq. (31)
     Partial *part;        // per-chunk partials
-    const void *tab;      // forcing table, k < spp + 16 (float/double), see drive_at
-
-    uint64_t n_paths;
-    uint64_t n0, n1;      // step range of this launch
-    uint64_t n_window;
-    uint32_t spp;         // period of the forcing table in steps (1: no periodic drive)
-    uint32_t point;
-    uint32_t key0, key1;
+    PointConst p;
+    uint64_t n0, n1;      // step range of this launch (export: first path, count)
     uint32_t snapshot;    // store the window snapshot at the end of the launch
-
-    double dt, gamma, F, L;
-    double g3;            // G sqrt(3 dt)
-    double bias;          // lambda zeta
-    double lam_dt;        // lambda dt
-    double zeta;
-    double Fa, Fb;
-    double mua_dt, mub_dt;
-    double p_hi;          // stationary Pr{+Fb} = mu_a / (mu_a + mu_b)
-    double x0_lo, x0_w, v0_lo, v0_w;
+    uint32_t pad;
     double t_window;      // (n - n_window) dt for the velocity kernel
 };
 

@@ -106,29 +106,69 @@ template <typename R> struct KickEntry {
     R z;            // amplitude; < 0 marks "draw inline from here"
 };
 
-// Algorithm 3 draw for kick number k: next waiting time s (steps, FP64 decision)
-// and amplitude z = zeta E.  Kick k uses words (2(k%2), 2(k%2)+1) of block k/2.
+// Exponential countdown s = floor(E / (rate dt)), E = -ln(1 - phi), phi = w 2^-32,
+// decided exactly as in FP64 (the oracle's expression).  FP32 paths first form
+// an FP32 estimate X32 with v_log_f32; its error is below
+// 3e-7 / (rate dt) + 4.2e-7 X (rounding of 1 - phi, log2 near 1, the scale), and
+// the tolerance tol0 + tol1 X is several times that, so floor(X32) is exact
+// unless X32 lies within the tolerance of an integer -- then FP64 decides.
 template <typename R>
-__device__ __forceinline__ void kick_draw(const KArgs &a, uint32_t path, uint32_t k, uint32_t &s, R &z)
+__device__ __forceinline__ uint32_t countdown(uint32_t w, double rate_dt, float c, float tol0, float tol1)
+{
+    if constexpr (sizeof(R) == 4) {
+        const float one_minus_phi = ((float)(~w) + 1.0f) * 0x1p-32f;   // (2^32 - w) 2^-32
+        const float X = -__builtin_amdgcn_logf(one_minus_phi) * c;
+        const float fl = floorf(X);
+        const float fr = X - fl;
+        const float tol = fmaf(tol1, X, tol0);
+        if (fr > tol && fr < 1.0f - tol) return (uint32_t)fl;
+    }
+    return (uint32_t)floor(expo64(w) / rate_dt);
+}
+
+// Kick amplitude z = zeta E (no decision depends on it: FP32 paths use v_log_f32).
+template <typename R> __device__ __forceinline__ R amplitude(const PointConst &a, uint32_t w)
+{
+    if constexpr (sizeof(R) == 4) {
+        const float one_minus_phi = ((float)(~w) + 1.0f) * 0x1p-32f;
+        return __builtin_amdgcn_logf(one_minus_phi) * a.zeta_ln2;
+    } else {
+        return a.zeta * expo64(w);
+    }
+}
+
+// Algorithm 3 draw for kick number k: next waiting time s (steps) and amplitude z.
+// Kick k uses words (2(k%2), 2(k%2)+1) of block k/2.
+template <typename R>
+__device__ __forceinline__ void kick_from(const PointConst &a, uint32_t ws, uint32_t wz, uint32_t &s, R &z)
+{
+    s = countdown<R>(ws, a.lam_dt, a.c_lam, a.tol0_lam, a.tol1);
+    z = amplitude<R>(a, wz);
+}
+
+template <typename R>
+__device__ __forceinline__ void kick_draw(const PointConst &a, uint32_t path, uint32_t k, uint32_t &s, R &z)
 {
     const U4 q = philox4x32_10(k >> 1, path, a.point, TAG_POISSON, a.key0, a.key1);
     const bool second = (k & 1u) != 0u;
-    s = (uint32_t)floor(expo64(second ? q.z : q.x) / a.lam_dt);
-    z = (R)(a.zeta * expo64(second ? q.w : q.y));
+    kick_from<R>(a, second ? q.z : q.x, second ? q.w : q.y, s, z);
 }
 
-// Algorithm 4 draw for flip number m into state d_new: dwell s (steps, FP64).
-__device__ __forceinline__ uint32_t flip_draw(const KArgs &a, uint32_t path, uint32_t m, int32_t d_new)
+// Algorithm 4 draw for flip number m into state d_new: dwell s (steps).
+template <typename R>
+__device__ __forceinline__ uint32_t flip_draw(const PointConst &a, uint32_t path, uint32_t m, int32_t d_new)
 {
     const U4 q = philox4x32_10(m >> 2, path, a.point, TAG_DICH, a.key0, a.key1);
-    const double mu_dt = d_new ? a.mub_dt : a.mua_dt;
-    return (uint32_t)floor(expo64(pick(q, m & 3u)) / mu_dt);
+    const uint32_t w = pick(q, m & 3u);
+    return d_new ? countdown<R>(w, a.mub_dt, a.c_mub, a.tol0_mub, a.tol1)
+                 : countdown<R>(w, a.mua_dt, a.c_mua, a.tol0_mua, a.tol1);
 }
 
 // Queue the kicks of one window.  `off` is the offset of the next kick (the
 // Algorithm 3 countdown at the window start).  q[slot * qs] is this lane's queue.
+// One Philox block holds two kicks: an iteration uses both halves when it can.
 template <typename R>
-__device__ __forceinline__ void kick_window(const KArgs &a, uint32_t path, uint32_t wlen, uint32_t off,
+__device__ __forceinline__ void kick_window(const PointConst &a, uint32_t path, uint32_t wlen, uint32_t off,
                                             uint32_t &kP, KickEntry<R> *q, uint32_t qs)
 {
     uint32_t slot = 0;
@@ -136,14 +176,24 @@ __device__ __forceinline__ void kick_window(const KArgs &a, uint32_t path, uint3
     while (__any(active)) {
         if (active) {
             if (slot < JCAP) {
+                const U4 b = philox4x32_10(kP >> 1, path, a.point, TAG_POISSON, a.key0, a.key1);
+                const bool second = (kP & 1u) != 0u;
                 uint32_t sn;
                 R z;
-                kick_draw<R>(a, path, kP, sn, z);
+                kick_from<R>(a, second ? b.z : b.x, second ? b.w : b.y, sn, z);
                 q[slot * qs] = KickEntry<R>{off, z};
                 ++slot;
                 ++kP;
                 off = off + 1u + sn;
                 active = off < wlen;
+                if (!second && active && slot < JCAP) {      // the block's second kick
+                    kick_from<R>(a, b.z, b.w, sn, z);
+                    q[slot * qs] = KickEntry<R>{off, z};
+                    ++slot;
+                    ++kP;
+                    off = off + 1u + sn;
+                    active = off < wlen;
+                }
             } else {
                 active = false;      // queue full: the rest of the window is drawn inline
             }
@@ -153,7 +203,8 @@ __device__ __forceinline__ void kick_window(const KArgs &a, uint32_t path, uint3
 }
 
 // Queue the flips of one window; bit INLINE_BIT marks "draw inline from here".
-__device__ __forceinline__ void flip_window(const KArgs &a, uint32_t path, uint32_t wlen, uint32_t off,
+template <typename R>
+__device__ __forceinline__ void flip_window(const PointConst &a, uint32_t path, uint32_t wlen, uint32_t off,
                                             uint32_t &mD, int32_t d, uint32_t *q, uint32_t qs)
 {
     uint32_t slot = 0;
@@ -162,7 +213,7 @@ __device__ __forceinline__ void flip_window(const KArgs &a, uint32_t path, uint3
         if (active) {
             if (slot < JCAP) {
                 d = 1 - d;
-                const uint32_t sn = flip_draw(a, path, mD, d);
+                const uint32_t sn = flip_draw<R>(a, path, mD, d);
                 q[slot * qs] = off;
                 ++slot;
                 ++mD;

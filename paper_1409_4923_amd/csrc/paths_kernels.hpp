@@ -36,7 +36,7 @@ __device__ __forceinline__ void store_path(const KArgs &a, uint32_t p, const Pat
 // Constant-within-step forcing at phase k: drive + tilt - Poisson bias + potential
 // offset, from the host-built table (period a.spp >= 1, extended by 16 entries so
 // that the 17 values of a 16-step block are contiguous).
-template <typename R> __device__ __forceinline__ R drive_at(const KArgs &a, uint32_t k)
+template <typename R> __device__ __forceinline__ R drive_at(const PointConst &a, uint32_t k)
 {
     return reinterpret_cast<const R *>(a.tab)[k];
 }
@@ -45,16 +45,16 @@ template <typename R> __device__ __forceinline__ R drive_at(const KArgs &a, uint
 template <typename R> struct JumpCursor {
     uint32_t nP;    // offset of the next kick in the window
     R zP;           // its amplitude (< 0: kicks are drawn inline from nP on)
-    uint32_t cP;    // next queue slot
+    uint32_t cP;    // element index of the next queue slot (slot * qs)
     uint32_t nD;    // offset of the next flip
-    uint32_t cD;    // next queue slot (FLIP_INLINE: flips drawn inline)
+    uint32_t cD;    // element index of the next queue slot (FLIP_INLINE: drawn inline)
 };
 constexpr uint32_t FLIP_INLINE = 0xFFFFFFFFu;
 
 // One step of one path at window offset `off`: jumps due at this step, then
 // Algorithm 1.  `dxi` is the Algorithm 2 increment.  (Folding is done by the caller.)
 template <typename R, int DYN, int POT, int NOISE>
-__device__ __forceinline__ void full_step(const KArgs &a, uint32_t path, Path<R> &s, JumpCursor<R> &J,
+__device__ __forceinline__ void full_step(const PointConst &a, uint32_t path, Path<R> &s, JumpCursor<R> &J,
                                           const KickEntry<R> *kq, const uint32_t *fq, uint32_t qs,
                                           uint32_t off, R dxi, R h, R hh, R ngam, R A0, R A1, R Fa, R Fb)
 {
@@ -63,8 +63,8 @@ __device__ __forceinline__ void full_step(const KArgs &a, uint32_t path, Path<R>
         if (J.nP == off) {                       // Algorithm 3: s <= 0 at this step
             if (J.zP >= R(0)) {
                 z = J.zP;
-                const KickEntry<R> e = kq[J.cP * qs];
-                ++J.cP;
+                const KickEntry<R> e = kq[J.cP];
+                J.cP += qs;
                 J.nP = e.off;
                 J.zP = e.z;
             } else {
@@ -79,12 +79,12 @@ __device__ __forceinline__ void full_step(const KArgs &a, uint32_t path, Path<R>
         if (J.nD == off) {                       // Algorithm 4: s <= 0 at this step
             s.d = 1 - s.d;
             if (J.cD != FLIP_INLINE) {
-                const uint32_t e = fq[J.cD * qs];
-                ++J.cD;
+                const uint32_t e = fq[J.cD];
+                J.cD += qs;
                 if (e & INLINE_BIT) J.cD = FLIP_INLINE;
                 J.nD = e & ~INLINE_BIT;
             } else {
-                const uint32_t sn = flip_draw(a, path, s.mD, s.d);
+                const uint32_t sn = flip_draw<R>(a, path, s.mD, s.d);
                 ++s.mD;
                 J.nD = off + 1u + sn;
             }
@@ -112,44 +112,33 @@ template <typename R, int NOISE> constexpr uint32_t queue_bytes()
 }
 
 // ---------------------------------------------------------------------------
-// Integration kernel: advances paths over steps [n0, n1) in windows of JW steps
-// (aligned to multiples of JW).  Per window the jumps are queued, then the steps
-// run in blocks of 16 sharing one Philox call for Algorithm 2 (4 words x 4
-// base-6 digits).  Lane layout: path = (blockIdx.x * PPL + j) * blockDim.x + tid.
-// Dynamic LDS: the jump queues, slot-major (slot * PPL * blockDim + column).
+// The integration loop: advances PPL paths per lane over steps [n0, n1) in
+// windows of JW steps (aligned to multiples of JW).  Per window the jumps are
+// queued, then the steps run in blocks of 16 sharing one Philox call for
+// Algorithm 2 (4 words x 4 base-6 digits) and 17 scalar loads of the forcing
+// table; x is folded after every step whose index is a multiple of 16.
+// smem holds the jump queues, slot-major with stride qs; column col(j) is this
+// lane's j-th path.
 // ---------------------------------------------------------------------------
 template <typename R, int DYN, int POT, int NOISE, int PPL>
-__global__ void __launch_bounds__(512) k_advance(const KArgs a)
+__device__ __forceinline__ void advance_range(const PointConst &a, const uint32_t (&path)[PPL],
+                                              Path<R> (&s)[PPL], uint64_t n0, uint64_t n1,
+                                              unsigned char *smem, uint32_t qs, uint32_t col0)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const uint32_t base = blockIdx.x * PPL * blockDim.x + threadIdx.x;
-    if ((uint64_t)base >= a.n_paths) return;
-    const uint32_t qs = PPL * blockDim.x;
     KickEntry<R> *kq = reinterpret_cast<KickEntry<R> *>(smem);
     uint32_t *fq = reinterpret_cast<uint32_t *>(
         smem + (((NOISE & NZ_POISSON) != 0) ? (JCAP + 1) * qs * sizeof(KickEntry<R>) : 0));
-
-    uint32_t path[PPL];
-    bool valid[PPL];
-    Path<R> s[PPL];
     JumpCursor<R> J[PPL];
-#pragma unroll
-    for (int j = 0; j < PPL; ++j) {
-        const uint64_t p = (uint64_t)base + (uint64_t)j * blockDim.x;
-        valid[j] = p < a.n_paths;
-        path[j] = valid[j] ? (uint32_t)p : base;
-        load_path<R, POT, NOISE>(a, path[j], s[j]);
-    }
     const R h = (R)a.dt, hh = (R)(0.5 * a.dt), ngam = (R)(-a.gamma), g3 = (R)a.g3;
     const R Fa = (R)a.Fa, Fb = (R)a.Fb;
+    const uint32_t wave_cols = qs / PPL;
+    auto col = [&](int j) { return (uint32_t)j * wave_cols + col0; };
 
-    uint64_t n = a.n0;
+    uint64_t n = n0;
     uint32_t k = (uint32_t)(n % a.spp);           // drive phase of step n
 
-    auto col = [&](int j) { return (uint32_t)j * blockDim.x + threadIdx.x; };
-
-    while (n < a.n1) {
-        const uint64_t wend = ((n / JW) + 1u) * JW < a.n1 ? ((n / JW) + 1u) * JW : a.n1;
+    while (n < n1) {
+        const uint64_t wend = ((n / JW) + 1u) * JW < n1 ? ((n / JW) + 1u) * JW : n1;
         const uint32_t wlen = (uint32_t)(wend - n);
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
@@ -158,13 +147,13 @@ __global__ void __launch_bounds__(512) k_advance(const KArgs a)
                 const KickEntry<R> e = kq[col(j)];
                 J[j].nP = e.off;
                 J[j].zP = e.z;
-                J[j].cP = 1u;
+                J[j].cP = qs;                       // element index of slot 1
             }
             if constexpr ((NOISE & NZ_DICH) != 0) {
-                flip_window(a, path[j], wlen, (uint32_t)s[j].sD, s[j].mD, s[j].d, fq + col(j), qs);
+                flip_window<R>(a, path[j], wlen, (uint32_t)s[j].sD, s[j].mD, s[j].d, fq + col(j), qs);
                 const uint32_t e = fq[col(j)];
                 J[j].nD = e & ~INLINE_BIT;
-                J[j].cD = (e & INLINE_BIT) ? FLIP_INLINE : 1u;
+                J[j].cD = (e & INLINE_BIT) ? FLIP_INLINE : qs;
             }
         }
         uint32_t off = 0;
@@ -245,44 +234,72 @@ __global__ void __launch_bounds__(512) k_advance(const KArgs a)
             if constexpr ((NOISE & NZ_DICH) != 0) s[j].sD = (int32_t)(J[j].nD - wlen);
         }
     }
+}
 
+// Ensemble integration kernel: lane layout path = (blockIdx.x * PPL + j) * blockDim.x + tid.
+template <typename R, int DYN, int POT, int NOISE, int PPL>
+__global__ void __launch_bounds__(512) k_advance(const KArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t base = blockIdx.x * PPL * blockDim.x + threadIdx.x;
+    if (base >= a.p.n_paths) return;
+    uint32_t path[PPL];
+    bool valid[PPL];
+    Path<R> s[PPL];
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+        const uint64_t p = (uint64_t)base + (uint64_t)j * blockDim.x;
+        valid[j] = p < a.p.n_paths;
+        path[j] = valid[j] ? (uint32_t)p : base;
+        load_path<R, POT, NOISE>(a, path[j], s[j]);
+    }
+    advance_range<R, DYN, POT, NOISE, PPL>(a.p, path, s, a.n0, a.n1, smem, PPL * blockDim.x, threadIdx.x);
 #pragma unroll
     for (int j = 0; j < PPL; ++j)
         if (valid[j]) store_path<R, POT, NOISE>(a, path[j], s[j]);
 }
 
 // ---------------------------------------------------------------------------
-// Initial conditions (tag 2), computed in FP64 and stored in the path precision.
+// Initial conditions (tag 2), computed in FP64 and stored in the path precision:
+// x ~ U[x0_lo, x0_hi) folded, v ~ U[v0_lo, v0_hi), Poisson countdown
+// floor(E / (lambda dt)), dichotomous state opposite to a stationary draw with
+// countdown 0 (the first step flips into the stationary state).
 // ---------------------------------------------------------------------------
 template <typename R, int DYN, int POT, int NOISE>
-__global__ void __launch_bounds__(256) k_init(const KArgs a)
+__device__ __forceinline__ Path<R> init_path(const PointConst &a, uint32_t p)
 {
-    const uint64_t p64 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p64 >= a.n_paths) return;
-    const uint32_t p = (uint32_t)p64;
     const U4 q = philox4x32_10(0u, p, a.point, TAG_INIT, a.key0, a.key1);
     const double L = period<POT>();
     double x = a.x0_lo + a.x0_w * ((double)q.x * 0x1p-32);
     const double kf = floor(x / L);
     x = x - kf * L;
-    int32_t w = (int32_t)kf;
-    R xr = (R)x;
-    if (xr >= (R)L) { xr -= (R)L; w += 1; }   // rounding to the path precision may reach L
-    const double v = (DYN == DYN_INERTIAL) ? a.v0_lo + a.v0_w * ((double)q.y * 0x1p-32) : 0.0;
-    arr<R>(a.x)[p] = xr;
-    a.w[p] = w;
-    arr<R>(a.v)[p] = (R)v;
-    if constexpr ((NOISE & NZ_POISSON) != 0) {
-        a.sP[p] = (int32_t)floor(expo64(q.z) / a.lam_dt);
-        a.kP[p] = 0u;
-    }
+    Path<R> s;
+    s.w = (int32_t)kf;
+    s.x = (R)x;
+    if (s.x >= (R)L) { s.x -= (R)L; s.w += 1; }   // rounding to the path precision may reach L
+    s.v = (DYN == DYN_INERTIAL) ? (R)(a.v0_lo + a.v0_w * ((double)q.y * 0x1p-32)) : R(0);
+    s.sP = 0; s.kP = 0u; s.sD = 0; s.mD = 0u; s.d = 0;
+    if constexpr ((NOISE & NZ_POISSON) != 0) s.sP = (int32_t)floor(expo64(q.z) / a.lam_dt);
     if constexpr ((NOISE & NZ_DICH) != 0) {
         const int32_t dstar = ((double)q.w * 0x1p-32 < a.p_hi) ? 1 : 0;
-        a.d[p] = 1 - dstar;    // step 0 flips into dstar and draws its dwell
-        a.sD[p] = 0;
-        a.mD[p] = 0u;
+        s.d = 1 - dstar;
     }
-    if (a.snapshot) { arr<R>(a.xi)[p] = xr; a.wi[p] = w; }
+    return s;
+}
+
+template <typename R, int DYN, int POT, int NOISE>
+__global__ void __launch_bounds__(256) k_init(const KArgs a)
+{
+    const uint64_t p64 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p64 >= a.p.n_paths) return;
+    const uint32_t p = (uint32_t)p64;
+    const Path<R> s = init_path<R, DYN, POT, NOISE>(a.p, p);
+    arr<R>(a.x)[p] = s.x;
+    a.w[p] = s.w;
+    arr<R>(a.v)[p] = s.v;
+    if constexpr ((NOISE & NZ_POISSON) != 0) { a.sP[p] = s.sP; a.kP[p] = s.kP; }
+    if constexpr ((NOISE & NZ_DICH) != 0) { a.d[p] = s.d; a.sD[p] = s.sD; a.mD[p] = s.mD; }
+    if (a.snapshot) { arr<R>(a.xi)[p] = s.x; a.wi[p] = s.w; }
 }
 
 // ---------------------------------------------------------------------------
@@ -295,7 +312,7 @@ __global__ void __launch_bounds__(256) k_velocity(const KArgs a)
     const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const double L = period<POT>();
     double vp = 0.0;
-    bool have = p < a.n_paths;
+    bool have = p < a.p.n_paths;
     if (have) {
         const double dx = (double)(a.w[p] - a.wi[p]) * L +
                           ((double)arr<R>(a.x)[p] - (double)arr<R>(a.xi)[p]);
@@ -322,7 +339,7 @@ __global__ void __launch_bounds__(256) k_velocity(const KArgs a)
         bad += __shfl_xor(bad, off, 64);
     }
     const uint64_t chunk = p >> 6;
-    if ((threadIdx.x & 63u) == 0u && (chunk << 6) < a.n_paths) {
+    if ((threadIdx.x & 63u) == 0u && (chunk << 6) < a.p.n_paths) {
         a.part[chunk] = Partial{s1.hi, s1.lo, s2.hi, s2.lo, cnt, bad};
     }
 }

@@ -106,6 +106,19 @@ def test_fp64_per_path_high_jump_rates(dyn, noise):
         assert_close(ps.v.numpy(), v, what="v")
 
 
+@pytest.mark.parametrize("noise", [W.POISSON, W.DICH])
+def test_fp32_jump_decisions_equal_fp64_kernel(noise):
+    """The FP32 kernels decide countdowns from an FP32 estimate with an FP64 fallback near
+    integer boundaries; over ~3e7 draws the integer jump state equals the FP64 kernel's."""
+    base = W.Workload(name="decisions", dyn=W.OVERDAMPED, pot=W.POT_FREE, noise=noise, prec=W.F64,
+                      n_paths=1 << 16, n_steps=2000, n_window=0, lam=25.0, zeta=0.02,
+                      Fa=0.5, Fb=0.5, mua=20.0, mub=25.0, dt=0.01, seed=99)
+    say("FP32 vs FP64 kernel jump decisions, noise=%d, 65536 paths x 2000 steps" % noise)
+    _, a = gpu_run(base, [2000])
+    _, b = gpu_run(base.with_(prec=W.F32), [2000])
+    assert np.array_equal(a.noise.numpy(), b.noise.numpy())
+
+
 @pytest.mark.parametrize("w", [W.C2, W.C3], ids=["c2-model", "c3-model"])
 def test_fp64_per_path_jump_models(w):
     w = w.with_(prec=W.F64, n_paths=4096)
