@@ -121,9 +121,9 @@ typedef struct bm_stats {
 
 typedef struct bm_tune {
     uint32_t size;            /* = sizeof(bm_tune)                                         */
-    uint32_t paths_per_lane;  /* 1 or 2                                                    */
+    uint32_t paths_per_lane;  /* 1 or 2 (2: FP32 paths only)                               */
     uint32_t block;           /* work-group size: 64, 128, 256, 512                         */
-    uint32_t reserved;
+    uint32_t groups_per_cu;   /* persistent scan: work-groups per CU (0: as many as fit)   */
 } bm_tune;
 
 typedef struct bm_ensemble bm_ensemble;
@@ -152,7 +152,9 @@ int bm_ensemble_create(const bm_model *model, const bm_run *run, void *d_ws, siz
 /* Release the handle (host metadata only; the workspace stays the caller's). */
 int bm_ensemble_destroy(bm_ensemble *e);
 
-/* Choose the launch shape (NULL restores the default).  Results never depend on it. */
+/* Choose the launch shape (NULL: the default for this model, see bm_tune_set_default).
+ * Results never depend on it.  BM_ERR_UNSUPPORTED if the jump queues of the shape
+ * exceed 64 KiB of LDS per work-group. */
 int bm_ensemble_set_tune(bm_ensemble *e, const bm_tune *tune);
 
 /* Advance every path by n_steps steps of Algorithm 1 (with Algorithms 2-4 for
@@ -179,6 +181,55 @@ int bm_reduce(bm_ensemble *e, bm_stats *d_out);
  * steps done > window_start (else it is left untouched). */
 int bm_read_paths(bm_ensemble *e, uint64_t first, uint64_t count,
                   double *d_x, double *d_v, int64_t *d_noise, double *d_vp);
+
+/* ------------------------------------------------------------------------- */
+/* Batched parameter scan (Sec. 4, Execution configuration optimizations: the  */
+/* stochastic dynamics solved for many parameter values in one kernel call).   */
+/* ------------------------------------------------------------------------- */
+typedef struct bm_scan_plan bm_scan_plan;
+
+/* Bytes of device workspace for a scan over the n_points (models[i], runs[i])
+ * pairs (multiple of 256; enough for any launch shape).  Every point must pass
+ * the checks of bm_ensemble_workspace_size, have n_steps > window_start, and share
+ * dyn, pot, noise and prec with the others (else BM_ERR_UNSUPPORTED). */
+int bm_scan_workspace_size(const bm_model *models, const bm_run *runs, size_t n_points, size_t *bytes);
+
+/* Plan a scan: upload the per-point constants and FP64-built forcing tables to
+ * d_ws, order the work items -- chunks of 64 paths (128 with two paths per lane)
+ * of every point -- longest horizon first, and capture into a hipGraph
+ * [reset the work counter; one persistent work-stealing launch in which every
+ * wave claims items with an atomic add and integrates them with the ensemble
+ * path's code; one per-point reduction].  Point i's result goes to d_results[i]
+ * (n_points bm_stats, device) and is bit-identical to bm_integrate(runs[i].n_steps)
+ * + bm_reduce on an ensemble of that point.  tune: NULL = bm_tune_get_default.
+ * Returns once the upload is complete (it synchronises `stream`). */
+int bm_scan_plan_create(const bm_model *models, const bm_run *runs, size_t n_points, const bm_tune *tune,
+                        void *d_ws, size_t ws_bytes, bm_stats *d_results, void *stream, bm_scan_plan **out);
+
+/* Enqueue one replay of the plan's graph on its stream (results overwritten). */
+int bm_scan_plan_launch(bm_scan_plan *plan);
+
+/* Release the plan (graph and host metadata; the workspace stays the caller's). */
+int bm_scan_plan_destroy(bm_scan_plan *plan);
+
+/* One-shot scan: plan, launch, wait for the launch, release (synchronises `stream`). */
+int bm_scan(const bm_model *models, const bm_run *runs, size_t n_points, const bm_tune *tune,
+            void *d_ws, size_t ws_bytes, bm_stats *d_results, void *stream);
+
+/* Autotuner: times every launch shape (paths per lane 1/2 for FP32, block 64..512,
+ * occupancy-limited groups per CU) on copies of the points with horizons capped at
+ * max_steps (window = second half), on `stream`, and stores the fastest in *best
+ * (and as the default for this (dyn, pot, noise, prec)).  *best_ms, if not NULL,
+ * receives its time.  Synchronises `stream`.  The workspace must fit the scan. */
+int bm_scan_autotune(const bm_model *models, const bm_run *runs, size_t n_points, uint64_t max_steps,
+                     void *d_ws, size_t ws_bytes, bm_stats *d_results, void *stream,
+                     bm_tune *best, float *best_ms);
+
+/* Default launch shape per (dyn, pot, noise, prec) for this process (used when
+ * a call gets no bm_tune); the built-in default is 1 path per lane, block 256,
+ * groups_per_cu 0. */
+int bm_tune_set_default(uint32_t dyn, uint32_t pot, uint32_t noise, uint32_t prec, const bm_tune *tune);
+int bm_tune_get_default(uint32_t dyn, uint32_t pot, uint32_t noise, uint32_t prec, bm_tune *out);
 
 #ifdef __cplusplus
 }

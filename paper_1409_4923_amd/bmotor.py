@@ -53,7 +53,7 @@ class bm_stats(ctypes.Structure):
 
 class bm_tune(ctypes.Structure):
     _fields_ = [("size", ctypes.c_uint32), ("paths_per_lane", ctypes.c_uint32),
-                ("block", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("block", ctypes.c_uint32), ("groups_per_cu", ctypes.c_uint32)]
 
 
 STATS_BYTES = ctypes.sizeof(bm_stats)
@@ -81,6 +81,16 @@ SIGNATURES = [
     ("bm_ensemble_steps", ctypes.c_int, [_vp, _P(ctypes.c_uint64)]),
     ("bm_reduce", ctypes.c_int, [_vp, _vp]),
     ("bm_read_paths", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_uint64, _vp, _vp, _vp, _vp]),
+    ("bm_scan_workspace_size", ctypes.c_int, [_P(bm_model), _P(bm_run), _sz, _P(_sz)]),
+    ("bm_scan_plan_create", ctypes.c_int, [_P(bm_model), _P(bm_run), _sz, _P(bm_tune), _vp, _sz, _vp, _vp,
+                                           _P(_vp)]),
+    ("bm_scan_plan_launch", ctypes.c_int, [_vp]),
+    ("bm_scan_plan_destroy", ctypes.c_int, [_vp]),
+    ("bm_scan", ctypes.c_int, [_P(bm_model), _P(bm_run), _sz, _P(bm_tune), _vp, _sz, _vp, _vp]),
+    ("bm_scan_autotune", ctypes.c_int, [_P(bm_model), _P(bm_run), _sz, ctypes.c_uint64, _vp, _sz, _vp, _vp,
+                                        _P(bm_tune), _P(ctypes.c_float)]),
+    ("bm_tune_set_default", ctypes.c_int, [ctypes.c_uint32] * 4 + [_P(bm_tune)]),
+    ("bm_tune_get_default", ctypes.c_int, [ctypes.c_uint32] * 4 + [_P(bm_tune)]),
 ]
 
 
@@ -127,11 +137,12 @@ def make_run(**kw) -> bm_run:
     return r
 
 
-def make_tune(paths_per_lane: int = 1, block: int = 256) -> bm_tune:
+def make_tune(paths_per_lane: int = 1, block: int = 256, groups_per_cu: int = 0) -> bm_tune:
     t = bm_tune()
     t.size = ctypes.sizeof(bm_tune)
     t.paths_per_lane = paths_per_lane
     t.block = block
+    t.groups_per_cu = groups_per_cu
     return t
 
 
@@ -258,3 +269,103 @@ def stats_from_bytes(b: bytes) -> bm_stats:
     s = bm_stats()
     ctypes.memmove(ctypes.byref(s), b, STATS_BYTES)
     return s
+
+
+# ---------------------------------------------------------------------------
+# Batched scan
+# ---------------------------------------------------------------------------
+def _arrays(models, runs):
+    n = len(models)
+    assert n == len(runs) and n > 0
+    M = (bm_model * n)(*models)
+    R = (bm_run * n)(*runs)
+    return M, R, n
+
+
+def bm_scan_workspace_size(models, runs) -> int:
+    M, R, n = _arrays(models, runs)
+    b = ctypes.c_size_t()
+    check(lib().bm_scan_workspace_size(M, R, n, ctypes.byref(b)))
+    return int(b.value)
+
+
+def bm_scan_plan_create(models, runs, tune, d_ws: int, ws_bytes: int, d_results: int, stream: int) -> int:
+    M, R, n = _arrays(models, runs)
+    h = ctypes.c_void_p()
+    check(lib().bm_scan_plan_create(M, R, n, ctypes.byref(tune) if tune is not None else None, d_ws, ws_bytes,
+                                    d_results, stream, ctypes.byref(h)))
+    return int(h.value)
+
+
+def bm_scan_plan_launch(h: int) -> None:
+    check(lib().bm_scan_plan_launch(h))
+
+
+def bm_scan_plan_destroy(h: int) -> None:
+    check(lib().bm_scan_plan_destroy(h))
+
+
+def bm_scan(models, runs, tune, d_ws: int, ws_bytes: int, d_results: int, stream: int) -> None:
+    M, R, n = _arrays(models, runs)
+    check(lib().bm_scan(M, R, n, ctypes.byref(tune) if tune is not None else None, d_ws, ws_bytes, d_results,
+                        stream))
+
+
+def bm_scan_autotune(models, runs, max_steps: int, d_ws: int, ws_bytes: int, d_results: int, stream: int):
+    M, R, n = _arrays(models, runs)
+    t = bm_tune()
+    ms = ctypes.c_float()
+    check(lib().bm_scan_autotune(M, R, n, max_steps, d_ws, ws_bytes, d_results, stream, ctypes.byref(t),
+                                 ctypes.byref(ms)))
+    return t, float(ms.value)
+
+
+def bm_tune_set_default(dyn: int, pot: int, noise: int, prec: int, tune: bm_tune) -> None:
+    check(lib().bm_tune_set_default(dyn, pot, noise, prec, ctypes.byref(tune)))
+
+
+def bm_tune_get_default(dyn: int, pot: int, noise: int, prec: int) -> bm_tune:
+    t = bm_tune()
+    check(lib().bm_tune_get_default(dyn, pot, noise, prec, ctypes.byref(t)))
+    return t
+
+
+def stats_array_from_bytes(b: bytes, n: int):
+    arr = (bm_stats * n)()
+    ctypes.memmove(arr, b, STATS_BYTES * n)
+    return list(arr)
+
+
+class Scan:
+    """A planned scan over (bm_model, bm_run) pairs; workspace and results are torch tensors."""
+
+    def __init__(self, models, runs, tune: bm_tune | None = None, device=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        self.models, self.runs = list(models), list(runs)
+        self.n = len(self.models)
+        self.ws_bytes = bm_scan_workspace_size(self.models, self.runs)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.results = torch.empty(self.n * STATS_BYTES, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.h = bm_scan_plan_create(self.models, self.runs, tune, self.ws.data_ptr(), self.ws_bytes,
+                                     self.results.data_ptr(), self.stream.cuda_stream)
+
+    def launch(self):
+        bm_scan_plan_launch(self.h)
+
+    def stats(self):
+        self.stream.synchronize()
+        return stats_array_from_bytes(self.results.cpu().numpy().tobytes(), self.n)
+
+    def close(self):
+        if getattr(self, "h", None):
+            bm_scan_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -31,6 +31,11 @@ SOURCES = [
     ("paths_f32_in.hip", []),
     ("paths_f64_od.hip", []),
     ("paths_f64_in.hip", []),
+    ("scan.hip", ["-ffp-contract=off"]),
+    ("scan_f32_od.hip", []),
+    ("scan_f32_in.hip", []),
+    ("scan_f64_od.hip", []),
+    ("scan_f64_in.hip", []),
 ]
 
 

@@ -14,15 +14,21 @@
 #include "common.hpp"
 #include "launch.hpp"
 #include "paths.hpp"
+#include "reduce.hpp"
+#include "host.hpp"
 
 using namespace bm;
+using namespace bm::host;
 
 // ---------------------------------------------------------------------------
 // Errors
 // ---------------------------------------------------------------------------
+namespace bm {
+namespace host {
+
 static thread_local std::string g_err;
 
-static int fail(int code, const char *fmt, ...)
+int fail(int code, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -33,19 +39,18 @@ static int fail(int code, const char *fmt, ...)
     return code;
 }
 
-static int ok()
+int ok()
 {
     g_err.clear();
     return BM_OK;
 }
 
-static int hip_fail(hipError_t e, const char *what)
+int hip_fail(hipError_t e, const char *what)
 {
     return fail(BM_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-extern "C" uint32_t bm_abi_version(void) { return BM_ABI_VERSION; }
-extern "C" const char *bm_last_error(void) { return g_err.c_str(); }
+const char *last_error_text() { return g_err.c_str(); }
 
 // ---------------------------------------------------------------------------
 // Validation and derived constants
@@ -55,7 +60,7 @@ static bool fin(double v) { return std::isfinite(v); }
 // Largest countdown an exponential variate can produce: E = -ln(1 - phi) <= 32 ln 2.
 static constexpr double E_MAX = 22.18070977791825;
 
-static int validate(const bm_model *m, const bm_run *r)
+int validate(const bm_model *m, const bm_run *r)
 {
     if (!m || !r) return fail(BM_ERR_INVALID_ARG, "model and run must not be NULL");
     if (m->size != sizeof(bm_model)) return fail(BM_ERR_INVALID_ARG, "bm_model.size mismatch");
@@ -107,14 +112,14 @@ static int validate(const bm_model *m, const bm_run *r)
     return BM_OK;
 }
 
-static double step_of(const bm_model *m, const bm_run *r)
+double step_of(const bm_model *m, const bm_run *r)
 {
     return r->steps_per_period > 0 ? (2.0 * M_PI / m->drive_omega) / (double)r->steps_per_period
                                    : r->dt;
 }
 
 // Entries of the forcing table: one drive period plus one block of 16 steps.
-static size_t table_entries(const bm_run *r) { return (r->steps_per_period ? r->steps_per_period : 1u) + 16; }
+size_t table_entries(const bm_run *r) { return (r->steps_per_period ? r->steps_per_period : 1u) + 16; }
 
 // ---------------------------------------------------------------------------
 // Workspace layout (structure of arrays, each 256-byte aligned)
@@ -162,7 +167,7 @@ extern "C" int bm_ensemble_workspace_size(const bm_model *model, const bm_run *r
 // ---------------------------------------------------------------------------
 // Device check: the kernels are built for gfx950 only.
 // ---------------------------------------------------------------------------
-static int check_device(int *dev_out)
+int check_device(int *dev_out)
 {
     int n = 0;
     hipError_t e = hipGetDeviceCount(&n);
@@ -180,6 +185,12 @@ static int check_device(int *dev_out)
     return BM_OK;
 }
 
+} // namespace host
+} // namespace bm
+
+extern "C" uint32_t bm_abi_version(void) { return BM_ABI_VERSION; }
+extern "C" const char *bm_last_error(void) { return last_error_text(); }
+
 // ---------------------------------------------------------------------------
 // Ensemble handle
 // ---------------------------------------------------------------------------
@@ -196,8 +207,11 @@ struct bm_ensemble {
     std::vector<float> tab32;
 };
 
+namespace bm {
+namespace host {
+
 // Constant part of the forcing without a drive: tilt - Poisson bias + potential offset.
-static double forcing_constant(const bm_model *m)
+double forcing_constant(const bm_model *m)
 {
     const double bias = (m->noise & BM_NOISE_POISSON) ? m->shot_rate * m->shot_mean : 0.0;
     const double pot_off = m->pot == BM_POT_RATCHET ? -M_PI : 0.0;
@@ -207,7 +221,7 @@ static double forcing_constant(const bm_model *m)
 // Table of the constant-within-step forcing per drive phase, in FP64:
 // a cos(2 pi k / spp) + F - lambda zeta + potential offset, k = 0 .. spp-1,
 // followed by 16 entries repeating the start (one block of steps).
-static void forcing_table(const bm_model *m, const bm_run *r, std::vector<double> &tab)
+void forcing_table(const bm_model *m, const bm_run *r, std::vector<double> &tab)
 {
     const uint32_t spp = r->steps_per_period;
     const uint32_t per = spp ? spp : 1u;
@@ -221,7 +235,7 @@ static void forcing_table(const bm_model *m, const bm_run *r, std::vector<double
 
 
 // Per-point constants shared by the ensemble and scan kernels.
-static PointConst point_const(const bm_model *m, const bm_run *r, const void *d_tab)
+PointConst point_const(const bm_model *m, const bm_run *r, const void *d_tab)
 {
     PointConst k;
     std::memset(&k, 0, sizeof k);
@@ -267,6 +281,9 @@ static PointConst point_const(const bm_model *m, const bm_run *r, const void *d_
     return k;
 }
 
+} // namespace host
+} // namespace bm
+
 static void fill_kargs(bm_ensemble *e)
 {
     KArgs &k = e->k;
@@ -309,8 +326,9 @@ extern "C" int bm_ensemble_create(const bm_model *model, const bm_run *run, void
     e->ws = (char *)d_ws;
     e->stream = (hipStream_t)stream;
     e->n_done = 0;
-    e->ppl = 1;
-    e->block = 256;
+    const bm_tune dt = default_tune(model->dyn, model->pot, model->noise, run->prec);
+    e->ppl = dt.paths_per_lane;
+    e->block = dt.block;
     fill_kargs(e);
     fill_table(e);
 
@@ -344,32 +362,14 @@ extern "C" int bm_ensemble_destroy(bm_ensemble *e)
     return ok();
 }
 
-// LDS of the jump queues of one work-group (see queue_bytes in paths_kernels.hpp).
-static size_t queue_lds_bytes(uint32_t noise, uint32_t prec, uint32_t ppl, uint32_t block)
-{
-    const size_t kick = prec == BM_F32 ? sizeof(KickEntry<float>) : sizeof(KickEntry<double>);
-    size_t per = 0;
-    if (noise & BM_NOISE_POISSON) per += (JCAP + 1) * kick;
-    if (noise & BM_NOISE_DICH) per += (JCAP + 1) * 4;
-    return per * ppl * block;
-}
-
 extern "C" int bm_ensemble_set_tune(bm_ensemble *e, const bm_tune *t)
 {
     if (!e) return fail(BM_ERR_INVALID_ARG, "NULL handle");
-    if (!t) { e->ppl = 1; e->block = 256; return ok(); }
-    if (t->size != sizeof(bm_tune)) return fail(BM_ERR_INVALID_ARG, "bm_tune.size mismatch");
-    if (t->paths_per_lane != 1 && t->paths_per_lane != 2)
-        return fail(BM_ERR_INVALID_ARG, "paths_per_lane must be 1 or 2");
-    if (t->paths_per_lane == 2 && e->run.prec != BM_F32)
-        return fail(BM_ERR_UNSUPPORTED, "paths_per_lane = 2 is built for FP32 paths only");
-    if (t->block != 64 && t->block != 128 && t->block != 256 && t->block != 512)
-        return fail(BM_ERR_INVALID_ARG, "block must be 64, 128, 256 or 512");
-    if (queue_lds_bytes(e->model.noise, e->run.prec, t->paths_per_lane, t->block) > 65536)
-        return fail(BM_ERR_UNSUPPORTED, "jump queues of %u x %u lanes exceed 64 KiB of LDS",
-                    t->paths_per_lane, t->block);
-    e->ppl = t->paths_per_lane;
-    e->block = t->block;
+    const bm_tune use = t ? *t : default_tune(e->model.dyn, e->model.pot, e->model.noise, e->run.prec);
+    int rc = check_tune(&use, e->model.noise, e->run.prec);
+    if (rc) return rc;
+    e->ppl = use.paths_per_lane;
+    e->block = use.block;
     return ok();
 }
 
@@ -414,69 +414,10 @@ extern "C" int bm_integrate(bm_ensemble *e, uint64_t n_steps)
     return ok();
 }
 
-// ---------------------------------------------------------------------------
-// Reduction: chunk partials combined in a fixed order by one work-group.
-// ---------------------------------------------------------------------------
-__device__ static void finish_stats(DD s1, DD s2, uint64_t n, uint64_t bad, double tw, bm_stats *out)
-{
-    bm_stats st;
-    st.n = n;
-    st.n_nonfinite = bad;
-    st.t_window = tw;
-    const double nn = (double)n;
-    if (n == 0) {
-        st.mean = st.var = st.se = __builtin_nan("");
-    } else {
-        // mean = s1 / n as a double-double
-        const double mh = s1.hi / nn;
-        const double r = ((s1.hi - mh * nn) - fma(mh, nn, -(mh * nn))) + s1.lo;
-        const double ml = r / nn;
-        st.mean = mh + ml;
-        if (n < 2) {
-            st.var = st.se = __builtin_nan("");
-        } else {
-            // s2 - s1 * mean, with the product kept to double-double accuracy
-            const double p = s1.hi * mh;
-            const double pe = fma(s1.hi, mh, -p) + (s1.hi * ml + s1.lo * mh);
-            const DD num = dd_add(s2, DD{-p, -pe});
-            const double var = (num.hi + num.lo) / (nn - 1.0);
-            st.var = var;
-            st.se = sqrt(var / nn);
-        }
-    }
-    *out = st;
-}
-
 __global__ void __launch_bounds__(256) k_reduce_final(const Partial *part, uint64_t n_chunks, double tw,
                                                       bm_stats *out)
 {
-    __shared__ double l1h[256], l1l[256], l2h[256], l2l[256];
-    __shared__ uint64_t lc[256], lb[256];
-    const uint32_t t = threadIdx.x;
-    const uint64_t lo = n_chunks * t / 256, hi = n_chunks * (t + 1) / 256;
-    DD s1{0.0, 0.0}, s2{0.0, 0.0};
-    uint64_t c = 0, b = 0;
-    for (uint64_t i = lo; i < hi; ++i) {
-        const Partial q = part[i];
-        s1 = dd_add(s1, DD{q.s1_hi, q.s1_lo});
-        s2 = dd_add(s2, DD{q.s2_hi, q.s2_lo});
-        c += q.n;
-        b += q.n_bad;
-    }
-    l1h[t] = s1.hi; l1l[t] = s1.lo; l2h[t] = s2.hi; l2l[t] = s2.lo; lc[t] = c; lb[t] = b;
-    __syncthreads();
-    for (uint32_t st = 128; st >= 1; st >>= 1) {
-        if (t < st) {
-            const DD a1{l1h[t], l1l[t]}, b1{l1h[t + st], l1l[t + st]};
-            const DD a2{l2h[t], l2l[t]}, b2{l2h[t + st], l2l[t + st]};
-            const DD r1 = dd_add(a1, b1), r2 = dd_add(a2, b2);
-            l1h[t] = r1.hi; l1l[t] = r1.lo; l2h[t] = r2.hi; l2l[t] = r2.lo;
-            lc[t] += lc[t + st];
-            lb[t] += lb[t + st];
-        }
-        __syncthreads();
-    }
-    if (t == 0) finish_stats(DD{l1h[0], l1l[0]}, DD{l2h[0], l2l[0]}, lc[0], lb[0], tw, out);
+    reduce_chunks(part, n_chunks, tw, out);
 }
 
 static void set_window(bm_ensemble *e, KArgs &k)

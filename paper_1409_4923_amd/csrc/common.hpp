@@ -70,6 +70,7 @@ struct DD { double hi, lo; };
 
 __device__ __forceinline__ DD dd_add(DD a, DD b)
 {
+#pragma clang fp contract(off)
     const double s = a.hi + b.hi;
     const double bb = s - a.hi;
     const double e = (a.hi - (s - bb)) + (b.hi - bb);

@@ -6,10 +6,14 @@
 
 namespace bm {
 
+struct ScanArgs;
+
 #define BM_DECLARE_LAUNCHERS(SUF)                                                                 \
     hipError_t launch_init_##SUF(int pot, int noise, const KArgs &a, hipStream_t s);               \
     hipError_t launch_advance_##SUF(int pot, int noise, int ppl, int block, const KArgs &a,       \
-                                    hipStream_t s);
+                                    hipStream_t s);                                                \
+    hipError_t launch_scan_##SUF(int pot, int noise, int ppl, int block, int groups_per_cu,       \
+                                 int n_cu, const ScanArgs &a, hipStream_t s);
 
 BM_DECLARE_LAUNCHERS(f32_od)
 BM_DECLARE_LAUNCHERS(f32_in)

@@ -5,6 +5,7 @@
 #pragma once
 
 #include "paths.hpp"
+#include "reduce.hpp"
 
 namespace bm {
 
@@ -319,28 +320,10 @@ __global__ void __launch_bounds__(256) k_velocity(const KArgs a)
         vp = dx / a.t_window;
         a.vp[p] = vp;
     }
-    const bool fin = have && isfinite(vp);
-    DD s1 = dd_from(fin ? vp : 0.0);
-    DD s2 = dd_from(fin ? vp * vp : 0.0);
-    if (fin) {
-        // exact square as a double-double: vp*vp + fma residual
-        const double sq = vp * vp;
-        s2 = DD{sq, fma(vp, vp, -sq)};
-    }
-    uint32_t cnt = fin ? 1u : 0u;
-    uint32_t bad = (have && !fin) ? 1u : 0u;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        DD o1{__shfl_xor(s1.hi, off, 64), __shfl_xor(s1.lo, off, 64)};
-        DD o2{__shfl_xor(s2.hi, off, 64), __shfl_xor(s2.lo, off, 64)};
-        s1 = dd_add(s1, o1);
-        s2 = dd_add(s2, o2);
-        cnt += __shfl_xor(cnt, off, 64);
-        bad += __shfl_xor(bad, off, 64);
-    }
+    const Partial part = wave_partial(vp, have);
     const uint64_t chunk = p >> 6;
     if ((threadIdx.x & 63u) == 0u && (chunk << 6) < a.p.n_paths) {
-        a.part[chunk] = Partial{s1.hi, s1.lo, s2.hi, s2.lo, cnt, bad};
+        a.part[chunk] = part;
     }
 }
 

@@ -183,3 +183,66 @@ def test_create_checks_workspace_then_device():
         rc = L.bm_ensemble_create(ctypes.byref(m), ctypes.byref(r), 0x10000, need, None, ctypes.byref(h))
         assert rc == B.BM_ERR_DEVICE, B.last_error()
         assert h.value is None
+
+
+# ---------------------------------------------------------------------------
+# Scan entry points (no device calls)
+# ---------------------------------------------------------------------------
+def _scan_arrays(ws):
+    mr = [W.to_c(w) for w in ws]
+    M = (B.bm_model * len(ws))(*[m for m, _ in mr])
+    R = (B.bm_run * len(ws))(*[r for _, r in mr])
+    return M, R
+
+
+def test_scan_workspace_and_validation():
+    pts = W.c4_points(64)
+    M, R = _scan_arrays(pts)
+    n = ctypes.c_size_t()
+    assert B.lib().bm_scan_workspace_size(M, R, len(pts), ctypes.byref(n)) == B.BM_OK
+    assert n.value % 256 == 0
+    assert n.value >= sum((w.n_paths + 63) // 64 for w in pts) * 48
+    # empty scan, mixed models, empty window
+    assert B.lib().bm_scan_workspace_size(M, R, 0, ctypes.byref(n)) == B.BM_ERR_INVALID_ARG
+    M2, R2 = _scan_arrays([pts[0], pts[1].with_(pot=W.POT_RATCHET)])
+    assert B.lib().bm_scan_workspace_size(M2, R2, 2, ctypes.byref(n)) == B.BM_ERR_UNSUPPORTED
+    M3, R3 = _scan_arrays([pts[0].with_(n_window=pts[0].n_steps)])
+    assert B.lib().bm_scan_workspace_size(M3, R3, 1, ctypes.byref(n)) == B.BM_ERR_INVALID_ARG
+    assert "point 0" in B.last_error()
+
+
+def test_tune_defaults_roundtrip_and_checks():
+    t = B.bm_tune_get_default(W.INERTIAL, W.POT_SIN, W.GAUSS, W.F32)
+    assert (t.paths_per_lane, t.block, t.groups_per_cu) == (1, 256, 0)
+    B.bm_tune_set_default(W.INERTIAL, W.POT_SIN, W.GAUSS, W.F32, B.make_tune(2, 128, 3))
+    t = B.bm_tune_get_default(W.INERTIAL, W.POT_SIN, W.GAUSS, W.F32)
+    assert (t.paths_per_lane, t.block, t.groups_per_cu) == (2, 128, 3)
+    B.bm_tune_set_default(W.INERTIAL, W.POT_SIN, W.GAUSS, W.F32, B.make_tune())
+    with pytest.raises(B.BMError) as ex:
+        B.bm_tune_set_default(W.INERTIAL, W.POT_SIN, W.GAUSS, W.F64, B.make_tune(2, 256))
+    assert ex.value.code == B.BM_ERR_UNSUPPORTED
+    with pytest.raises(B.BMError) as ex:
+        B.bm_tune_set_default(W.INERTIAL, W.POT_SIN, W.GAUSS, W.F32, B.make_tune(1, 100))
+    assert ex.value.code == B.BM_ERR_INVALID_ARG
+    with pytest.raises(B.BMError) as ex:      # FP64 Poisson + dichotomous queues of 512 lanes > 64 KiB
+        B.bm_tune_set_default(W.INERTIAL, W.POT_SIN, 7, W.F64, B.make_tune(1, 512))
+    assert ex.value.code == B.BM_ERR_UNSUPPORTED
+
+
+def test_scan_plan_needs_device_and_workspace():
+    pts = W.c4_points(4)
+    M, R = _scan_arrays(pts)
+    h = ctypes.c_void_p()
+    need = ctypes.c_size_t()
+    B.lib().bm_scan_workspace_size(M, R, 4, ctypes.byref(need))
+    L = B.lib()
+    assert L.bm_scan_plan_create(M, R, 4, None, 0x10000, need.value - 256, 0x20000, None,
+                                 ctypes.byref(h)) == B.BM_ERR_WORKSPACE
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except Exception:
+        has_gpu = False
+    if not has_gpu:
+        assert L.bm_scan_plan_create(M, R, 4, None, 0x10000, need.value, 0x20000, None,
+                                     ctypes.byref(h)) == B.BM_ERR_DEVICE
