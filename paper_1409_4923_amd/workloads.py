@@ -120,3 +120,38 @@ def to_c(w: Workload):
                    n_paths=w.n_paths, seed=w.seed, x0_lo=w.x0_lo, x0_hi=w.x0_hi,
                    v0_lo=w.v0_lo, v0_hi=w.v0_hi)
     return m, r
+
+
+# ---------------------------------------------------------------------------
+# Surrogate inputs
+# ---------------------------------------------------------------------------
+MLP_IN, MLP_H = 5, 256
+MLP_NPARAM = MLP_H * MLP_IN + MLP_H + 2 * (MLP_H * MLP_H + MLP_H) + MLP_H + 1   # 133377
+
+
+def mlp_params(n_members: int, seed: int = 0) -> np.ndarray:
+    """Initial parameters [n_members, 133377] (float32): every weight and bias of a layer
+    with fan-in f drawn from U(-1/sqrt(f), 1/sqrt(f)), packed W1|b1|W2|b2|W3|b3|W4|b4."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((n_members, MLP_NPARAM), dtype=np.float32)
+    fans = [(MLP_H * MLP_IN, MLP_IN), (MLP_H, MLP_IN), (MLP_H * MLP_H, MLP_H), (MLP_H, MLP_H),
+            (MLP_H * MLP_H, MLP_H), (MLP_H, MLP_H), (MLP_H, MLP_H), (1, MLP_H)]
+    for m in range(n_members):
+        parts = [rng.uniform(-1.0, 1.0, n) / np.sqrt(f) for n, f in fans]
+        out[m] = np.concatenate(parts).astype(np.float32)
+    return out
+
+
+def surrogate_queries(n: int, seed: int = 0, gamma_range=(0.5, 2.0)) -> np.ndarray:
+    """Query points [n, 5] = (a, omega, F, D, gamma) over the surrogate's domain:
+    a ~ U[0,8], omega ~ U[1,10], F ~ U[-0.5,0.5], D log-uniform in [1e-4, 1e-1],
+    gamma ~ U[gamma_range] (float32)."""
+    rng = np.random.default_rng(seed)
+    u = rng.random((n, 5))
+    x = np.empty((n, 5))
+    x[:, 0] = 8.0 * u[:, 0]
+    x[:, 1] = 1.0 + 9.0 * u[:, 1]
+    x[:, 2] = u[:, 2] - 0.5
+    x[:, 3] = 10.0 ** (-4.0 + 3.0 * u[:, 3])
+    x[:, 4] = gamma_range[0] + (gamma_range[1] - gamma_range[0]) * u[:, 4]
+    return x.astype(np.float32)
