@@ -105,6 +105,107 @@ def oracle_baseline(w, seconds: float, threads: int):
                 mean_v=s.mean, se=s.se, n_paths=S)
 
 
+def scan_leg(args):
+    """Batched scan of the 4096-point inertial workload: autotune on short horizons,
+    then one graph launch timed with HIP events on the plan's stream."""
+    import torch
+    from paper_1409_4923_amd import bmotor as B
+    from paper_1409_4923_amd import workloads as W
+    pts = W.c4_points()
+    mr = [W.to_c(w) for w in pts]
+    models, runs = [m for m, _ in mr], [r for _, r in mr]
+    nb = B.bm_scan_workspace_size(models, runs)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    res = torch.empty(len(pts) * B.STATS_BYTES, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    tune, tune_ms = B.bm_scan_autotune(models, runs, 2000, ws.data_ptr(), nb, res.data_ptr(), stream.cuda_stream)
+    t_tune = time.perf_counter() - t0
+    h = B.bm_scan_plan_create(models, runs, None, ws.data_ptr(), nb, res.data_ptr(), stream.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    B.bm_scan_plan_launch(h)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    B.bm_scan_plan_destroy(h)
+    sec = e0.elapsed_time(e1) / 1e3
+    st = B.stats_array_from_bytes(res.cpu().numpy().tobytes(), len(pts))
+    total = sum(w.path_steps() for w in pts)
+    ops, _ = algorithmic_work(pts[0])
+    print("scan leg: %.3g path-steps in %.3f s" % (total, sec), file=sys.stderr, flush=True)
+    return {"workload": "inertial-scan-4096-points", "n_points": len(pts), "path_steps": total,
+            "seconds": sec, "path_steps_per_s": total / sec, "points_per_s": len(pts) / sec,
+            "tune": {"paths_per_lane": tune.paths_per_lane, "block": tune.block,
+                     "groups_per_cu": tune.groups_per_cu, "autotune_s": t_tune},
+            "valu_frac": ops * total / sec / VALU_LANE_OPS_PEAK,
+            "n_nonfinite_points": int(sum(1 for x in st if not math.isfinite(x.mean)))}
+
+
+def surrogate_leg(args):
+    """Learned surrogate of <v>(a, omega, F, D, gamma) with Monte Carlo fallback.
+
+    Labels: args.labels points (gamma ~ U[0.5, 2]) by one batched scan at
+    args.label_paths paths x args.label_periods periods.  Truth: args.heldout points
+    at args.truth_paths x args.label_periods.  Plain-MC cost of a point at
+    |d<v>| <= 0.01 (3 SE <= 0.01): N = (3 sigma / 0.01)^2 paths of the same horizon
+    at the measured scan throughput.  Surrogate+fallback cost: the 10^6-query
+    routing time plus that MC cost for the routed fraction."""
+    import numpy as np
+    import torch
+    from paper_1409_4923_amd import bmotor as B
+    from paper_1409_4923_amd import surrogate as S
+    from paper_1409_4923_amd import workloads as W
+    thr, tol = 0.005, 0.01
+    xl = W.surrogate_queries(args.labels, seed=101)
+    lab = S.monte_carlo(xl, args.label_paths, args.label_periods, seed=1, first_point=0)
+    print("surrogate: %d labels in %.1f s" % (args.labels, lab.seconds), file=sys.stderr, flush=True)
+    sur = B.Surrogate(5, seed=7)
+    t0 = time.perf_counter()
+    hist = S.train(sur, xl, lab.mean, epochs=args.epochs, batch=1024, lr=2e-3, seed=3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    print("surrogate: trained in %.1f s, loss %.4g -> %.4g" % (t_train, hist[0], hist[-1]), file=sys.stderr,
+          flush=True)
+    xh = W.surrogate_queries(args.heldout, seed=202)
+    truth = S.monte_carlo(xh, args.truth_paths, args.label_periods, seed=2, first_point=1 << 24)
+    rate = truth.path_steps / truth.seconds                              # MC path-steps/s on this workload
+    n_steps = args.label_periods * S.SPP
+    need = np.maximum(64.0, np.ceil((3.0 * np.nan_to_num(truth.std, nan=1.0) / tol) ** 2))
+    mc_cost = float(np.mean(need) * n_steps / rate)                      # seconds per point at |d| <= tol
+    # surrogate accuracy on the held-out points it answers itself
+    xd = torch.tensor(xh, device="cuda")
+    mean, std, fidx, fcnt = sur.query(xd, thr)
+    mean, std = mean.cpu().numpy(), std.cpu().numpy()
+    keep = std <= thr
+    err = np.abs(mean - truth.mean)
+    # routing 10^6 queries
+    xq = torch.tensor(W.surrogate_queries(args.queries, seed=303), device="cuda")
+    sur.query(xq, thr)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    _, _, _, qcnt = sur.query(xq, thr)
+    e1.record()
+    torch.cuda.synchronize()
+    t_query = e0.elapsed_time(e1) / 1e3
+    f = int(qcnt.item()) / args.queries
+    sur_rate = args.queries / (t_query + f * args.queries * mc_cost)
+    mc_rate = 1.0 / mc_cost
+    flops = args.queries * 5 * 2 * (5 * 256 + 2 * 256 * 256 + 256)
+    return {"labels": args.labels, "label_budget": [args.label_paths, args.label_periods],
+            "label_seconds": lab.seconds, "train_seconds": t_train, "train_loss": [hist[0], hist[-1]],
+            "heldout": args.heldout, "truth_paths": args.truth_paths, "truth_se_median": float(np.median(truth.se)),
+            "queries": args.queries, "threshold": thr, "query_seconds": t_query,
+            "fallback_fraction": f, "answered_heldout": int(keep.sum()),
+            "abs_err_answered_p50": float(np.percentile(err[keep], 50)) if keep.any() else None,
+            "abs_err_answered_p95": float(np.percentile(err[keep], 95)) if keep.any() else None,
+            "within_tol_answered": float(np.mean(err[keep] <= tol)) if keep.any() else None,
+            "mc_points_per_s_at_tol": mc_rate, "surrogate_points_per_s_at_tol": sur_rate,
+            "gain": sur_rate / mc_rate,
+            "mlp_inference": {"achieved": flops / t_query / 1e12, "peak": 2500.0, "unit": "TFLOP/s (BF16 MFMA)",
+                              "frac": flops / t_query / 2.5e15}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,7 +216,27 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="scan,surrogate", help="extra legs: scan, surrogate (or none)")
+    ap.add_argument("--labels", type=int, default=200_000)
+    ap.add_argument("--label-paths", type=int, default=256)
+    ap.add_argument("--label-periods", type=int, default=100)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--heldout", type=int, default=10_000)
+    ap.add_argument("--truth-paths", type=int, default=4096)
+    ap.add_argument("--queries", type=int, default=1_000_000)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (for scaling HBM counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20)
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "read_bytes": n, "write_bytes": n}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(paths and parameter points shard trivially; see the design notes).", file=sys.stderr)
@@ -214,6 +335,11 @@ def main():
         rec["oracle_se_v"] = cb["se"]
         rec["mean_v_within_3se"] = abs(st.mean - cb["mean_v"]) <= 3 * math.hypot(st.se, cb["se"])
         rec["speedup_vs_oracle"] = value / cb["value"]
+    legs = [l for l in args.legs.split(",") if l and l != "none"]
+    if "scan" in legs:
+        rec["scan"] = scan_leg(args)
+    if "surrogate" in legs:
+        rec["surrogate"] = surrogate_leg(args)
     print(json.dumps(rec), flush=True)
 
 

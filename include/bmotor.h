@@ -231,6 +231,65 @@ int bm_scan_autotune(const bm_model *models, const bm_run *runs, size_t n_points
 int bm_tune_set_default(uint32_t dyn, uint32_t pot, uint32_t noise, uint32_t prec, const bm_tune *tune);
 int bm_tune_get_default(uint32_t dyn, uint32_t pot, uint32_t noise, uint32_t prec, bm_tune *out);
 
+/* ------------------------------------------------------------------------- */
+/* Learned surrogate of <v>(a, omega, F, D, gamma): an ensemble of MLPs         */
+/* 5 -> 256 -> 256 -> 256 -> 1 with tanh-GELU (Hendrycks & Gimpel), BF16       */
+/* weights and FP32 accumulation (the 256 x 256 layers on MFMA), trained with  */
+/* Adam (Kingma & Ba) on <v> values produced by bm_scan.  Plain Monte Carlo    */
+/* stays the fallback: bm_surrogate_query routes the queries whose ensemble    */
+/* spread exceeds a threshold.                                                  */
+/*                                                                             */
+/* Inputs x are rows (a, omega, F, D, gamma) of FP32, normalised inside onto   */
+/* [-1, 1] over a in [0, 8], omega in [1, 10], F in [-0.5, 0.5],               */
+/* log10 D in [-4, -1], gamma in [0.5, 2].                                      */
+/* Parameters: d_params [n_members][BM_MLP_PARAMS] FP32, per member            */
+/* W1[256][5] b1[256] W2[256][256] b2[256] W3[256][256] b3[256] W4[256] b4     */
+/* (row-major [out][in]).  BF16 weight copies: d_wbf [n_members][BM_MLP_BF16]  */
+/* = W1 | W2 | W3 | W4 (round to nearest even), refreshed by bm_mlp_cast and   */
+/* bm_mlp_adam.                                                                 */
+/* ------------------------------------------------------------------------- */
+#define BM_MLP_INPUTS 5
+#define BM_MLP_HIDDEN 256
+#define BM_MLP_PARAMS 133377
+#define BM_MLP_BF16 132608
+#define BM_MLP_MAX_MEMBERS 16
+
+/* Device workspace bytes for a forward / query (training = 0) or a backward
+ * (training = 1) over `batch` rows.  Training batches: multiple of 64, <= 65536. */
+int bm_mlp_workspace_size(uint32_t n_members, uint64_t batch, uint32_t training, size_t *bytes);
+
+/* Initial parameters: every weight and bias of a layer with fan-in f drawn from
+ * U(-1/sqrt(f), 1/sqrt(f)) with Philox (key = seed, tag 4).  Enqueued on stream. */
+int bm_mlp_init(uint32_t n_members, uint64_t seed, float *d_params, void *stream);
+
+/* BF16 copies of the weights of d_params into d_wbf. */
+int bm_mlp_cast(uint32_t n_members, const float *d_params, uint16_t *d_wbf, void *stream);
+
+/* Predictions d_y [n_members][batch] (FP32) for the rows d_x [batch][5]. */
+int bm_mlp_forward(uint32_t n_members, const float *d_params, const uint16_t *d_wbf, const float *d_x,
+                   uint64_t batch, float *d_y, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Gradient of each member's mean squared error over its minibatch:
+ * member m uses rows d_idx[m * batch + r] of d_x / d_t (d_idx NULL: rows 0..batch-1).
+ * Writes d_grad [n_members][BM_MLP_PARAMS] (FP32, layout of d_params) and, if not
+ * NULL, d_loss [n_members]. */
+int bm_mlp_backward(uint32_t n_members, const float *d_params, const uint16_t *d_wbf, const float *d_x,
+                    const float *d_t, const uint32_t *d_idx, uint64_t batch, float *d_grad, float *d_loss,
+                    void *d_ws, size_t ws_bytes, void *stream);
+
+/* One Adam step (step counts from 1; bias-corrected moments d_m, d_v, FP32) on
+ * d_params, followed by the BF16 copies in d_wbf. */
+int bm_mlp_adam(uint32_t n_members, float *d_params, const float *d_grad, float *d_m, float *d_v, uint16_t *d_wbf,
+                uint32_t step, float lr, float beta1, float beta2, float eps, void *stream);
+
+/* Ensemble query: d_mean / d_std [batch] = mean and population standard
+ * deviation of the members' predictions; the rows with std > threshold (or a
+ * non-finite std) are written to d_fallback_idx in increasing order (capacity
+ * batch) and their number to *d_fallback_count (device). */
+int bm_surrogate_query(uint32_t n_members, const float *d_params, const uint16_t *d_wbf, const float *d_x,
+                       uint64_t batch, float threshold, float *d_mean, float *d_std, uint32_t *d_fallback_idx,
+                       uint32_t *d_fallback_count, void *d_ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -91,7 +91,19 @@ SIGNATURES = [
                                         _P(bm_tune), _P(ctypes.c_float)]),
     ("bm_tune_set_default", ctypes.c_int, [ctypes.c_uint32] * 4 + [_P(bm_tune)]),
     ("bm_tune_get_default", ctypes.c_int, [ctypes.c_uint32] * 4 + [_P(bm_tune)]),
+    ("bm_mlp_workspace_size", ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, _P(_sz)]),
+    ("bm_mlp_init", ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint64, _vp, _vp]),
+    ("bm_mlp_cast", ctypes.c_int, [ctypes.c_uint32, _vp, _vp, _vp]),
+    ("bm_mlp_forward", ctypes.c_int, [ctypes.c_uint32, _vp, _vp, _vp, ctypes.c_uint64, _vp, _vp, _sz, _vp]),
+    ("bm_mlp_backward", ctypes.c_int, [ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint64, _vp, _vp, _vp,
+                                       _sz, _vp]),
+    ("bm_mlp_adam", ctypes.c_int, [ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint32, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp]),
+    ("bm_surrogate_query", ctypes.c_int, [ctypes.c_uint32, _vp, _vp, _vp, ctypes.c_uint64, ctypes.c_float, _vp,
+                                          _vp, _vp, _vp, _vp, _sz, _vp]),
 ]
+
+BM_MLP_INPUTS, BM_MLP_HIDDEN, BM_MLP_PARAMS, BM_MLP_BF16, BM_MLP_MAX_MEMBERS = 5, 256, 133377, 132608, 16
 
 
 def lib() -> ctypes.CDLL:
@@ -369,3 +381,114 @@ class Scan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Surrogate
+# ---------------------------------------------------------------------------
+def bm_mlp_workspace_size(n_members: int, batch: int, training: bool) -> int:
+    b = ctypes.c_size_t()
+    check(lib().bm_mlp_workspace_size(n_members, batch, int(training), ctypes.byref(b)))
+    return int(b.value)
+
+
+def bm_mlp_init(n_members: int, seed: int, d_params: int, stream: int) -> None:
+    check(lib().bm_mlp_init(n_members, seed, d_params, stream))
+
+
+def bm_mlp_cast(n_members: int, d_params: int, d_wbf: int, stream: int) -> None:
+    check(lib().bm_mlp_cast(n_members, d_params, d_wbf, stream))
+
+
+def bm_mlp_forward(n_members, d_params, d_wbf, d_x, batch, d_y, d_ws, ws_bytes, stream) -> None:
+    check(lib().bm_mlp_forward(n_members, d_params, d_wbf, d_x, batch, d_y, d_ws, ws_bytes, stream))
+
+
+def bm_mlp_backward(n_members, d_params, d_wbf, d_x, d_t, d_idx, batch, d_grad, d_loss, d_ws, ws_bytes,
+                    stream) -> None:
+    check(lib().bm_mlp_backward(n_members, d_params, d_wbf, d_x, d_t, d_idx, batch, d_grad, d_loss, d_ws,
+                                ws_bytes, stream))
+
+
+def bm_mlp_adam(n_members, d_params, d_grad, d_m, d_v, d_wbf, step, lr, beta1=0.9, beta2=0.999, eps=1e-8,
+                stream=None) -> None:
+    check(lib().bm_mlp_adam(n_members, d_params, d_grad, d_m, d_v, d_wbf, step, lr, beta1, beta2, eps, stream))
+
+
+def bm_surrogate_query(n_members, d_params, d_wbf, d_x, batch, threshold, d_mean, d_std, d_fidx, d_fcount, d_ws,
+                       ws_bytes, stream) -> None:
+    check(lib().bm_surrogate_query(n_members, d_params, d_wbf, d_x, batch, threshold, d_mean, d_std, d_fidx,
+                                   d_fcount, d_ws, ws_bytes, stream))
+
+
+class Surrogate:
+    """Ensemble MLP whose parameters, Adam moments and BF16 copies are torch tensors."""
+
+    def __init__(self, n_members: int = 5, params=None, seed: int = 0, device=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        self.n = n_members
+        self.stream = torch.cuda.current_stream(self.device)
+        s = self.stream.cuda_stream
+        self.params = torch.empty((n_members, BM_MLP_PARAMS), dtype=torch.float32, device=self.device)
+        if params is None:
+            bm_mlp_init(n_members, seed, self.params.data_ptr(), s)
+        else:
+            self.params.copy_(torch.as_tensor(params, dtype=torch.float32))
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.wbf = torch.empty((n_members, BM_MLP_BF16), dtype=torch.int16, device=self.device)
+        self.step = 0
+        self._ws = {}
+        self.cast()
+
+    def _workspace(self, batch: int, training: bool):
+        key = (batch, training)
+        if key not in self._ws:
+            nb = bm_mlp_workspace_size(self.n, batch, training)
+            self._ws = {key: self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)}
+        w = self._ws[key]
+        return w.data_ptr(), w.numel()
+
+    def cast(self):
+        bm_mlp_cast(self.n, self.params.data_ptr(), self.wbf.data_ptr(), self.stream.cuda_stream)
+
+    def forward(self, x):
+        x = x.contiguous()
+        B = x.shape[0]
+        y = self.torch.empty((self.n, B), dtype=self.torch.float32, device=self.device)
+        ws, nb = self._workspace(B, False)
+        bm_mlp_forward(self.n, self.params.data_ptr(), self.wbf.data_ptr(), x.data_ptr(), B, y.data_ptr(), ws, nb,
+                       self.stream.cuda_stream)
+        return y
+
+    def backward(self, x, t, idx=None):
+        B = idx.shape[1] if idx is not None else x.shape[0]
+        loss = self.torch.empty(self.n, dtype=self.torch.float32, device=self.device)
+        ws, nb = self._workspace(B, True)
+        bm_mlp_backward(self.n, self.params.data_ptr(), self.wbf.data_ptr(), x.data_ptr(), t.data_ptr(),
+                        idx.data_ptr() if idx is not None else None, B, self.grad.data_ptr(), loss.data_ptr(),
+                        ws, nb, self.stream.cuda_stream)
+        return loss
+
+    def adam(self, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step += 1
+        bm_mlp_adam(self.n, self.params.data_ptr(), self.grad.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+                    self.wbf.data_ptr(), self.step, lr, beta1, beta2, eps, self.stream.cuda_stream)
+
+    def query(self, x, threshold: float):
+        """(mean, std, fallback indices) for rows x [B, 5]."""
+        torch = self.torch
+        x = x.contiguous()
+        B = x.shape[0]
+        mean = torch.empty(B, dtype=torch.float32, device=self.device)
+        std = torch.empty(B, dtype=torch.float32, device=self.device)
+        fidx = torch.empty(B, dtype=torch.int32, device=self.device)
+        fcnt = torch.zeros(1, dtype=torch.int32, device=self.device)
+        ws, nb = self._workspace(B, False)
+        bm_surrogate_query(self.n, self.params.data_ptr(), self.wbf.data_ptr(), x.data_ptr(), B, threshold,
+                           mean.data_ptr(), std.data_ptr(), fidx.data_ptr(), fcnt.data_ptr(), ws, nb,
+                           self.stream.cuda_stream)
+        return mean, std, fidx, fcnt

@@ -36,6 +36,7 @@ SOURCES = [
     ("scan_f32_in.hip", []),
     ("scan_f64_od.hip", []),
     ("scan_f64_in.hip", []),
+    ("mlp.hip", []),
 ]
 
 

@@ -1,0 +1,566 @@
+// mlp.hip -- ensemble MLP surrogate: inference, training (back-propagation of the
+// mean squared error, Adam), ensemble statistics and the routing of uncertain
+// queries to the Monte Carlo fallback.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "bmotor.h"
+#include "common.hpp"
+#include "host.hpp"
+#include "mlp_kernels.hpp"
+
+using namespace bm;
+using namespace bm::host;
+using namespace bm::mlp;
+
+static_assert(NPARAM == BM_MLP_PARAMS, "parameter block differs from bmotor.h");
+static_assert(NBF == BM_MLP_BF16, "BF16 block differs from bmotor.h");
+static_assert(IN == BM_MLP_INPUTS && H == BM_MLP_HIDDEN, "shape differs from bmotor.h");
+
+namespace {
+
+constexpr uint64_t CHUNK = 65536;       // inference rows per pass (bounds the workspace)
+
+// ---------------------------------------------------------------------------
+// Small layers
+// ---------------------------------------------------------------------------
+// Layer 1 (5 -> 256) + GELU; block = one row, lane = output; grid (rows, members).
+// Row r of member m reads x[idx ? idx[m * idx_stride + r] : row0 + r].
+__global__ void __launch_bounds__(256) k_l1_fwd(const float *x, const uint32_t *idx, uint64_t idx_stride,
+                                                uint64_t row0, const bf16_t *wbf, const float *params,
+                                                int rows, float *u_out, float *z_out, bf16_t *a_out)
+{
+    const int r = blockIdx.x, m = blockIdx.y, o = threadIdx.x;
+    const uint64_t src = idx ? (uint64_t)idx[(uint64_t)m * idx_stride + r] : row0 + (uint64_t)r;
+    float u[IN];
+    normalise(x + src * IN, u);
+    const bf16_t *w = wbf + (uint64_t)m * NBF + BOFF_W1 + o * IN;
+    float z = params[(uint64_t)m * NPARAM + OFF_B1 + o];
+#pragma unroll
+    for (int j = 0; j < IN; ++j) z = fmaf(bf2f(w[j]), u[j], z);
+    const uint64_t row = (uint64_t)m * rows + r;
+    if (u_out && o < IN) u_out[row * IN + o] = u[o];
+    if (z_out) z_out[row * H + o] = z;
+    a_out[row * H + o] = f2bf(gelu(z));
+}
+
+// Layer 4 (256 -> 1): one wave per row; grid (ceil(rows / 4), members).
+__global__ void __launch_bounds__(256) k_l4_fwd(const bf16_t *a3, const bf16_t *wbf, const float *params, int rows,
+                                                float *y, uint64_t y_stride, uint64_t y_off)
+{
+    const int m = blockIdx.y, lane = threadIdx.x & 63;
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows) return;
+    const bf16_t *a = a3 + ((uint64_t)m * rows + r) * H;
+    const bf16_t *w = wbf + (uint64_t)m * NBF + BOFF_W4;
+    float s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s = fmaf(bf2f(a[lane * 4 + i]), bf2f(w[lane * 4 + i]), s);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) y[(uint64_t)m * y_stride + y_off + r] = s + params[(uint64_t)m * NPARAM + OFF_B4];
+}
+
+// dy = 2 (y - t) / B and per-block sums of (y - t)^2; grid (ceil(B / 256), members).
+__global__ void __launch_bounds__(256) k_loss(const float *y, const float *t, const uint32_t *idx,
+                                              uint64_t idx_stride, int B, float *dy, float *partial)
+{
+    __shared__ float red[256];
+    const int m = blockIdx.y, b = blockIdx.x * 256 + threadIdx.x;
+    float e2 = 0.0f;
+    if (b < B) {
+        const uint64_t src = idx ? (uint64_t)idx[(uint64_t)m * idx_stride + b] : (uint64_t)b;
+        const float e = y[(uint64_t)m * B + b] - t[src];
+        dy[(uint64_t)m * B + b] = 2.0f * e / (float)B;
+        e2 = e * e;
+    }
+    red[threadIdx.x] = e2;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(uint64_t)m * gridDim.x + blockIdx.x] = red[0];
+}
+
+// loss[m] = sum of the block partials / B (fixed order).
+__global__ void k_loss_final(const float *partial, int nblk, int B, float *loss)
+{
+    const int m = threadIdx.x;
+    float s = 0.0f;
+    for (int i = 0; i < nblk; ++i) s += partial[(uint64_t)m * nblk + i];
+    loss[m] = s / (float)B;
+}
+
+// Layer 4 backward: dW4, db4 (one block per member, lane = input), and
+// dz3 = dy W4 gelu'(z3) (grid (B, members)).
+__global__ void __launch_bounds__(256) k_l4_bwd_w(const float *dy, const bf16_t *a3, int B, float *grad)
+{
+    const int m = blockIdx.y, i = threadIdx.x;
+    float s = 0.0f, sb = 0.0f;
+    for (int b = 0; b < B; ++b) {
+        const float d = dy[(uint64_t)m * B + b];
+        s = fmaf(d, bf2f(a3[((uint64_t)m * B + b) * H + i]), s);
+        sb += d;
+    }
+    grad[(uint64_t)m * NPARAM + OFF_W4 + i] = s;
+    if (i == 0) grad[(uint64_t)m * NPARAM + OFF_B4] = sb;
+}
+
+__global__ void __launch_bounds__(256) k_l4_bwd_dz(const float *dy, const bf16_t *wbf, const float *z3, int B,
+                                                   bf16_t *dz3)
+{
+    const int b = blockIdx.x, m = blockIdx.y, i = threadIdx.x;
+    const uint64_t row = (uint64_t)m * B + b;
+    const float w = bf2f(wbf[(uint64_t)m * NBF + BOFF_W4 + i]);
+    dz3[row * H + i] = f2bf(dy[row] * w * gelu_grad(z3[row * H + i]));
+}
+
+// Bias gradient db[o] = sum_b dz[b][o]; one block per member, lane = o.
+__global__ void __launch_bounds__(256) k_bias_grad(const bf16_t *dz, int B, float *grad, int off)
+{
+    const int m = blockIdx.y, o = threadIdx.x;
+    float s = 0.0f;
+    for (int b = 0; b < B; ++b) s += bf2f(dz[((uint64_t)m * B + b) * H + o]);
+    grad[(uint64_t)m * NPARAM + off + o] = s;
+}
+
+// Layer 1 weights: dW1[o][j] = sum_b dz1[b][o] u[b][j], db1[o] = sum_b dz1[b][o].
+__global__ void __launch_bounds__(256) k_l1_bwd(const bf16_t *dz1, const float *u, int B, float *grad)
+{
+    const int m = blockIdx.y, o = threadIdx.x;
+    float s[IN] = {0.f, 0.f, 0.f, 0.f, 0.f}, sb = 0.0f;
+    for (int b = 0; b < B; ++b) {
+        const uint64_t row = (uint64_t)m * B + b;
+        const float d = bf2f(dz1[row * H + o]);
+        sb += d;
+#pragma unroll
+        for (int j = 0; j < IN; ++j) s[j] = fmaf(d, u[row * IN + j], s[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < IN; ++j) grad[(uint64_t)m * NPARAM + OFF_W1 + o * IN + j] = s[j];
+    grad[(uint64_t)m * NPARAM + OFF_B1 + o] = sb;
+}
+
+// BF16 index of parameter p of a member, or -1 for biases.
+__device__ __forceinline__ int bf_index(int p)
+{
+    if (p < OFF_B1) return BOFF_W1 + (p - OFF_W1);
+    if (p >= OFF_W2 && p < OFF_B2) return BOFF_W2 + (p - OFF_W2);
+    if (p >= OFF_W3 && p < OFF_B3) return BOFF_W3 + (p - OFF_W3);
+    if (p >= OFF_W4 && p < OFF_B4) return BOFF_W4 + (p - OFF_W4);
+    return -1;
+}
+
+__global__ void __launch_bounds__(256) k_cast(const float *params, bf16_t *wbf, uint64_t total)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    const uint64_t m = i / NPARAM;
+    const int p = (int)(i - m * NPARAM);
+    const int b = bf_index(p);
+    if (b >= 0) wbf[m * NBF + b] = f2bf(params[i]);
+}
+
+// Adam (Kingma & Ba) with bias-corrected moments, then the BF16 weight copy.
+__global__ void __launch_bounds__(256) k_adam(float *params, const float *grad, float *mo, float *ve, bf16_t *wbf,
+                                              uint64_t total, float lr, float b1, float b2, float eps, float c1,
+                                              float c2)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    const float g = grad[i];
+    const float m = b1 * mo[i] + (1.0f - b1) * g;
+    const float v = b2 * ve[i] + (1.0f - b2) * g * g;
+    mo[i] = m;
+    ve[i] = v;
+    const float p = params[i] - lr * (m * c1) / (sqrtf(v * c2) + eps);
+    params[i] = p;
+    const uint64_t mem = i / NPARAM;
+    const int b = bf_index((int)(i - mem * NPARAM));
+    if (b >= 0) wbf[mem * NBF + b] = f2bf(p);
+}
+
+// Initial parameters U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from Philox (tag 4).
+__global__ void __launch_bounds__(256) k_init_params(float *params, uint64_t total, uint32_t k0, uint32_t k1)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    const uint64_t m = i / NPARAM;
+    const int p = (int)(i - m * NPARAM);
+    const U4 q = philox4x32_10((uint32_t)p, (uint32_t)m, 0u, 4u, k0, k1);
+    const float u = (float)(q.x >> 8) * 0x1p-24f * 2.0f - 1.0f;
+    const float fan = (p < OFF_W2) ? (float)IN : (float)H;
+    params[i] = u / sqrtf(fan);
+}
+
+// Ensemble mean / population std over members and the routing flag; grid over rows.
+__global__ void __launch_bounds__(256) k_stats(const float *y, int members, uint64_t B, float thr, float *mean,
+                                               float *stdv, uint32_t *blk_count)
+{
+    const uint64_t b = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    bool flag = false;
+    if (b < B) {
+        float s = 0.0f;
+        for (int m = 0; m < members; ++m) s += y[(uint64_t)m * B + b];
+        const float mu = s / (float)members;
+        float v = 0.0f;
+        for (int m = 0; m < members; ++m) {
+            const float d = y[(uint64_t)m * B + b] - mu;
+            v = fmaf(d, d, v);
+        }
+        const float sd = sqrtf(v / (float)members);
+        mean[b] = mu;
+        stdv[b] = sd;
+        flag = !(sd <= thr);                    // NaN std also falls back
+    }
+    __shared__ uint32_t cnt[4];
+    const unsigned long long bal = __ballot(flag);
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) blk_count[blockIdx.x] = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+}
+
+// Exclusive scan of the block counts (one block, sequential chunks) and the total.
+__global__ void __launch_bounds__(256) k_scan_counts(uint32_t *blk, uint64_t nblk, uint32_t *total)
+{
+    __shared__ uint32_t part[256];
+    const uint64_t per = (nblk + 255) / 256;
+    const uint64_t lo = per * threadIdx.x, hi = lo + per < nblk ? lo + per : nblk;
+    uint32_t s = 0;
+    for (uint64_t i = lo; i < hi; ++i) s += blk[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int i = 0; i < 256; ++i) { const uint32_t c = part[i]; part[i] = acc; acc += c; }
+        *total = acc;
+    }
+    __syncthreads();
+    uint32_t acc = part[threadIdx.x];
+    for (uint64_t i = lo; i < hi; ++i) { const uint32_t c = blk[i]; blk[i] = acc; acc += c; }
+}
+
+// Scatter the flagged row indices in increasing order.
+__global__ void __launch_bounds__(256) k_compact(const float *stdv, uint64_t B, float thr, const uint32_t *blk_off,
+                                                 uint32_t *out)
+{
+    const uint64_t b = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool flag = b < B && !(stdv[b] <= thr);
+    __shared__ uint32_t cnt[4];
+    const unsigned long long bal = __ballot(flag);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) cnt[w] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t base = blk_off[blockIdx.x];
+    for (int i = 0; i < w; ++i) base += cnt[i];
+    const uint32_t rank = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+    if (flag) out[base + rank] = (uint32_t)b;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout
+// ---------------------------------------------------------------------------
+size_t up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct MlpLayout {
+    size_t u, z1, z2, z3, a1, a2, a3, y, dy, dz1, dz2, dz3, part, mean, stdv, blk, total;
+    uint64_t rows;    // rows per pass
+};
+
+MlpLayout mlp_layout(uint32_t nm, uint64_t batch, bool training)
+{
+    MlpLayout L{};
+    const uint64_t R = training ? batch : (batch < CHUNK ? batch : CHUNK);
+    L.rows = R;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o += up(bytes); return at; };
+    L.a1 = take(nm * R * H * 2);
+    L.a2 = take(nm * R * H * 2);
+    L.a3 = take(nm * R * H * 2);
+    L.y = take(nm * batch * 4);
+    if (training) {
+        L.u = take(nm * R * IN * 4);
+        L.z1 = take(nm * R * H * 4);
+        L.z2 = take(nm * R * H * 4);
+        L.z3 = take(nm * R * H * 4);
+        L.dy = take(nm * R * 4);
+        L.dz1 = take(nm * R * H * 2);
+        L.dz2 = take(nm * R * H * 2);
+        L.dz3 = take(nm * R * H * 2);
+        L.part = take(nm * ((R + 255) / 256) * 4);
+    } else {
+        L.blk = take(((batch + 255) / 256) * 4 + 4);
+    }
+    L.total = o;
+    return L;
+}
+
+int check_members(uint32_t nm)
+{
+    if (nm < 1 || nm > BM_MLP_MAX_MEMBERS)
+        return fail(BM_ERR_INVALID_ARG, "n_members must be in [1, %d]", BM_MLP_MAX_MEMBERS);
+    return BM_OK;
+}
+
+int check_ws(const MlpLayout &L, void *d_ws, size_t ws_bytes)
+{
+    if (!d_ws || ((uintptr_t)d_ws & 255u)) return fail(BM_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    if (ws_bytes < L.total) return fail(BM_ERR_WORKSPACE, "workspace %zu B < %zu B needed", ws_bytes, L.total);
+    return BM_OK;
+}
+
+template <int EPI, bool TA, bool TB>
+hipError_t gemm(const GemmArgs &g, int members, hipStream_t s)
+{
+    const dim3 grid((uint32_t)(g.N / TN), (uint32_t)((g.M + TM - 1) / TM), (uint32_t)members);
+    hipLaunchKernelGGL((k_gemm<EPI, TA, TB>), grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+GemmArgs gemm_args()
+{
+    GemmArgs g;
+    std::memset(&g, 0, sizeof g);
+    return g;
+}
+
+// Forward of `rows` rows through all members; y[m * y_stride + y_off + r].
+hipError_t forward_pass(uint32_t nm, const float *params, const bf16_t *wbf, const float *x, const uint32_t *idx,
+                        uint64_t idx_stride, uint64_t row0, int rows, char *ws, const MlpLayout &L, bool training,
+                        float *y, uint64_t y_stride, uint64_t y_off, hipStream_t s)
+{
+    bf16_t *a1 = (bf16_t *)(ws + L.a1), *a2 = (bf16_t *)(ws + L.a2), *a3 = (bf16_t *)(ws + L.a3);
+    float *u = training ? (float *)(ws + L.u) : nullptr;
+    float *z1 = training ? (float *)(ws + L.z1) : nullptr;
+    float *z2 = training ? (float *)(ws + L.z2) : nullptr;
+    float *z3 = training ? (float *)(ws + L.z3) : nullptr;
+    hipLaunchKernelGGL(k_l1_fwd, dim3((uint32_t)rows, nm), dim3(256), 0, s, x, idx, idx_stride, row0, wbf, params,
+                       rows, u, z1, a1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const bf16_t *ain[2] = {a1, a2};
+    bf16_t *aout[2] = {a2, a3};
+    float *zo[2] = {z2, z3};
+    const int woff[2] = {BOFF_W2, BOFF_W3}, boff[2] = {OFF_B2, OFF_B3};
+    for (int l = 0; l < 2; ++l) {
+        GemmArgs g = gemm_args();
+        g.A = ain[l]; g.a_mstride = (uint64_t)rows * H; g.lda = H;
+        g.B = wbf + woff[l]; g.b_mstride = NBF; g.ldb = H;
+        g.M = rows; g.N = H; g.K = H;
+        g.bias = params + boff[l]; g.bias_mstride = NPARAM;
+        g.zout = zo[l]; g.zout_mstride = (uint64_t)rows * H;
+        g.out_bf = aout[l]; g.out_mstride = (uint64_t)rows * H; g.ldc = H;
+        e = gemm<EPI_FWD, false, false>(g, (int)nm, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_l4_fwd, dim3((uint32_t)((rows + 3) / 4), nm), dim3(256), 0, s, a3, wbf, params, rows, y,
+                       y_stride, y_off);
+    return hipGetLastError();
+}
+
+} // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" int bm_mlp_workspace_size(uint32_t n_members, uint64_t batch, uint32_t training, size_t *bytes)
+{
+    int rc = check_members(n_members);
+    if (rc) return rc;
+    if (!bytes) return fail(BM_ERR_INVALID_ARG, "bytes must not be NULL");
+    if (batch < 1 || batch > 0xFFFFFFFFull) return fail(BM_ERR_INVALID_ARG, "batch must be in [1, 2^32 - 1]");
+    if (training && (batch % 64 != 0 || batch > 65536))
+        return fail(BM_ERR_INVALID_ARG, "training batch must be a multiple of 64 and <= 65536");
+    *bytes = mlp_layout(n_members, batch, training != 0).total;
+    return ok();
+}
+
+extern "C" int bm_mlp_init(uint32_t n_members, uint64_t seed, float *d_params, void *stream)
+{
+    int rc = check_members(n_members);
+    if (rc) return rc;
+    if (!d_params) return fail(BM_ERR_INVALID_ARG, "d_params must not be NULL");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    const uint64_t total = (uint64_t)n_members * NPARAM;
+    hipLaunchKernelGGL(k_init_params, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       d_params, total, (uint32_t)seed, (uint32_t)(seed >> 32));
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ok() : hip_fail(e, "bm_mlp_init");
+}
+
+extern "C" int bm_mlp_cast(uint32_t n_members, const float *d_params, uint16_t *d_wbf, void *stream)
+{
+    int rc = check_members(n_members);
+    if (rc) return rc;
+    if (!d_params || !d_wbf) return fail(BM_ERR_INVALID_ARG, "NULL pointer");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    const uint64_t total = (uint64_t)n_members * NPARAM;
+    hipLaunchKernelGGL(k_cast, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, (hipStream_t)stream, d_params,
+                       (bf16_t *)d_wbf, total);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ok() : hip_fail(e, "bm_mlp_cast");
+}
+
+extern "C" int bm_mlp_forward(uint32_t n_members, const float *d_params, const uint16_t *d_wbf, const float *d_x,
+                              uint64_t batch, float *d_y, void *d_ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_members(n_members);
+    if (rc) return rc;
+    if (!d_params || !d_wbf || !d_x || !d_y) return fail(BM_ERR_INVALID_ARG, "NULL pointer");
+    if (batch < 1 || batch > 0xFFFFFFFFull) return fail(BM_ERR_INVALID_ARG, "batch must be in [1, 2^32 - 1]");
+    const MlpLayout L = mlp_layout(n_members, batch, false);
+    rc = check_ws(L, d_ws, ws_bytes);
+    if (rc) return rc;
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    for (uint64_t r0 = 0; r0 < batch; r0 += L.rows) {
+        const int rows = (int)(batch - r0 < L.rows ? batch - r0 : L.rows);
+        hipError_t e = forward_pass(n_members, d_params, (const bf16_t *)d_wbf, d_x, nullptr, 0, r0, rows,
+                                    (char *)d_ws, L, false, d_y, batch, r0, s);
+        if (e != hipSuccess) return hip_fail(e, "bm_mlp_forward");
+    }
+    return ok();
+}
+
+extern "C" int bm_mlp_backward(uint32_t n_members, const float *d_params, const uint16_t *d_wbf, const float *d_x,
+                               const float *d_t, const uint32_t *d_idx, uint64_t batch, float *d_grad,
+                               float *d_loss, void *d_ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_members(n_members);
+    if (rc) return rc;
+    if (!d_params || !d_wbf || !d_x || !d_t || !d_grad) return fail(BM_ERR_INVALID_ARG, "NULL pointer");
+    if (batch < 64 || batch % 64 != 0 || batch > 65536)
+        return fail(BM_ERR_INVALID_ARG, "training batch must be a multiple of 64 and <= 65536");
+    const MlpLayout L = mlp_layout(n_members, batch, true);
+    rc = check_ws(L, d_ws, ws_bytes);
+    if (rc) return rc;
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)d_ws;
+    const int B = (int)batch;
+    const uint32_t nm = n_members;
+    const bf16_t *wbf = (const bf16_t *)d_wbf;
+    float *y = (float *)(ws + L.y), *dy = (float *)(ws + L.dy), *u = (float *)(ws + L.u);
+    float *z1 = (float *)(ws + L.z1), *z2 = (float *)(ws + L.z2), *z3 = (float *)(ws + L.z3);
+    bf16_t *a1 = (bf16_t *)(ws + L.a1), *a2 = (bf16_t *)(ws + L.a2), *a3 = (bf16_t *)(ws + L.a3);
+    bf16_t *dz1 = (bf16_t *)(ws + L.dz1), *dz2 = (bf16_t *)(ws + L.dz2), *dz3 = (bf16_t *)(ws + L.dz3);
+    float *part = (float *)(ws + L.part);
+
+    hipError_t e = forward_pass(nm, d_params, wbf, d_x, d_idx, batch, 0, B, ws, L, true, y, batch, 0, s);
+    const int nblk = (B + 255) / 256;
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_loss, dim3(nblk, nm), dim3(256), 0, s, y, d_t, d_idx, batch, B, dy, part);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && d_loss) {
+        hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(nm), 0, s, part, nblk, B, d_loss);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_l4_bwd_w, dim3(1, nm), dim3(256), 0, s, dy, a3, B, d_grad);
+        hipLaunchKernelGGL(k_l4_bwd_dz, dim3(B, nm), dim3(256), 0, s, dy, wbf, z3, B, dz3);
+        e = hipGetLastError();
+    }
+    // layers 3 and 2: weight gradients dW = dz^T a_prev, bias gradients, and dz_prev
+    const bf16_t *dzs[2] = {dz3, dz2};
+    bf16_t *dzp[2] = {dz2, dz1};
+    const bf16_t *aprev[2] = {a2, a1};
+    const float *zprev[2] = {z2, z1};
+    const int woff[2] = {OFF_W3, OFF_W2}, boff[2] = {OFF_B3, OFF_B2}, bwoff[2] = {BOFF_W3, BOFF_W2};
+    for (int l = 0; l < 2 && e == hipSuccess; ++l) {
+        GemmArgs g = gemm_args();
+        g.A = dzs[l]; g.a_mstride = (uint64_t)B * H; g.lda = H;          // (m = out, k = row): dz[k][m]
+        g.B = aprev[l]; g.b_mstride = (uint64_t)B * H; g.ldb = H;        // (k = row, n = in): a[k][n]
+        g.M = H; g.N = H; g.K = B;
+        g.out_f = d_grad + woff[l]; g.out_mstride = NPARAM; g.ldc = H;
+        e = gemm<EPI_STORE, true, true>(g, (int)nm, s);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_bias_grad, dim3(1, nm), dim3(256), 0, s, dzs[l], B, d_grad, boff[l]);
+        e = hipGetLastError();
+        if (e != hipSuccess) break;
+        GemmArgs d = gemm_args();
+        d.A = dzs[l]; d.a_mstride = (uint64_t)B * H; d.lda = H;          // (m = row, k = out)
+        d.B = wbf + bwoff[l]; d.b_mstride = NBF; d.ldb = H;              // (k = out, n = in): W[k][n]
+        d.M = B; d.N = H; d.K = H;
+        d.zin = zprev[l]; d.zin_mstride = (uint64_t)B * H; d.ldz = H;
+        d.out_bf = dzp[l]; d.out_mstride = (uint64_t)B * H; d.ldc = H;
+        e = gemm<EPI_DGRAD, false, true>(d, (int)nm, s);
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_l1_bwd, dim3(1, nm), dim3(256), 0, s, dz1, u, B, d_grad);
+        e = hipGetLastError();
+    }
+    return e == hipSuccess ? ok() : hip_fail(e, "bm_mlp_backward");
+}
+
+extern "C" int bm_mlp_adam(uint32_t n_members, float *d_params, const float *d_grad, float *d_m, float *d_v,
+                           uint16_t *d_wbf, uint32_t step, float lr, float beta1, float beta2, float eps,
+                           void *stream)
+{
+    int rc = check_members(n_members);
+    if (rc) return rc;
+    if (!d_params || !d_grad || !d_m || !d_v || !d_wbf) return fail(BM_ERR_INVALID_ARG, "NULL pointer");
+    if (step < 1) return fail(BM_ERR_INVALID_ARG, "step counts from 1");
+    if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return fail(BM_ERR_INVALID_ARG, "need lr > 0, 0 <= beta < 1, eps > 0");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    const uint64_t total = (uint64_t)n_members * NPARAM;
+    const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, (double)step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, (double)step)));
+    hipLaunchKernelGGL(k_adam, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, (hipStream_t)stream, d_params,
+                       d_grad, d_m, d_v, (bf16_t *)d_wbf, total, lr, beta1, beta2, eps, c1, c2);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ok() : hip_fail(e, "bm_mlp_adam");
+}
+
+extern "C" int bm_surrogate_query(uint32_t n_members, const float *d_params, const uint16_t *d_wbf,
+                                  const float *d_x, uint64_t batch, float threshold, float *d_mean, float *d_std,
+                                  uint32_t *d_fallback_idx, uint32_t *d_fallback_count, void *d_ws,
+                                  size_t ws_bytes, void *stream)
+{
+    int rc = check_members(n_members);
+    if (rc) return rc;
+    if (!d_params || !d_wbf || !d_x || !d_mean || !d_std || !d_fallback_idx || !d_fallback_count)
+        return fail(BM_ERR_INVALID_ARG, "NULL pointer");
+    if (batch < 1 || batch > 0xFFFFFFFFull) return fail(BM_ERR_INVALID_ARG, "batch must be in [1, 2^32 - 1]");
+    if (!(threshold >= 0)) return fail(BM_ERR_INVALID_ARG, "threshold must be >= 0");
+    const MlpLayout L = mlp_layout(n_members, batch, false);
+    rc = check_ws(L, d_ws, ws_bytes);
+    if (rc) return rc;
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)d_ws;
+    float *y = (float *)(ws + L.y);
+    hipError_t e = hipSuccess;
+    for (uint64_t r0 = 0; r0 < batch && e == hipSuccess; r0 += L.rows) {
+        const int rows = (int)(batch - r0 < L.rows ? batch - r0 : L.rows);
+        e = forward_pass(n_members, d_params, (const bf16_t *)d_wbf, d_x, nullptr, 0, r0, rows, ws, L, false, y,
+                         batch, r0, s);
+    }
+    const uint64_t nblk = (batch + 255) / 256;
+    uint32_t *blk = (uint32_t *)(ws + L.blk);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_stats, dim3((uint32_t)nblk), dim3(256), 0, s, y, (int)n_members, batch, threshold,
+                           d_mean, d_std, blk);
+        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(256), 0, s, blk, nblk, d_fallback_count);
+        hipLaunchKernelGGL(k_compact, dim3((uint32_t)nblk), dim3(256), 0, s, d_std, batch, threshold, blk,
+                           d_fallback_idx);
+        e = hipGetLastError();
+    }
+    return e == hipSuccess ? ok() : hip_fail(e, "bm_surrogate_query");
+}

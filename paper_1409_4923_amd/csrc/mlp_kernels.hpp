@@ -28,7 +28,7 @@ constexpr int BOFF_W1 = 0;
 constexpr int BOFF_W2 = BOFF_W1 + H * IN;
 constexpr int BOFF_W3 = BOFF_W2 + H * H;
 constexpr int BOFF_W4 = BOFF_W3 + H * H;
-constexpr int NBF = BOFF_W4 + H;          // 132864
+constexpr int NBF = BOFF_W4 + H;          // 132608
 
 typedef uint16_t bf16_t;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));

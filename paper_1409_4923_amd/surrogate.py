@@ -1,0 +1,116 @@
+"""Surrogate pipeline: labels from batched Monte Carlo scans, ensemble training,
+and queries answered by the surrogate or, where the members disagree, by Monte
+Carlo.  Orchestration only: every computation runs in libbmotor (bm_scan,
+bm_mlp_backward, bm_mlp_adam, bm_surrogate_query).
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import bmotor as B
+from . import workloads as W
+
+SPP = 200      # steps per drive period of the inertial model
+
+
+def point_workloads(x: np.ndarray, n_paths: int, periods: int, seed: int = 0, first_point: int = 0):
+    """Inertial-model workloads (Gaussian noise, FP32 paths) for rows x = (a, omega, F, D, gamma)."""
+    out = []
+    n_steps = periods * SPP
+    for i, r in enumerate(np.asarray(x, dtype=np.float64)):
+        out.append(W.Workload(name="q%d" % i, dyn=W.INERTIAL, pot=W.POT_SIN, noise=W.GAUSS, prec=W.F32,
+                              a=float(r[0]), omega=float(r[1]), F=float(r[2]), D=float(r[3]),
+                              gamma=float(r[4]), spp=SPP, n_paths=n_paths, n_steps=n_steps,
+                              n_window=n_steps // 2, seed=seed, point=first_point + i, x0_lo=0.0, x0_hi=1.0,
+                              v0_lo=-2.0, v0_hi=2.0))
+    return out
+
+
+@dataclass
+class MCResult:
+    mean: np.ndarray
+    se: np.ndarray
+    std: np.ndarray
+    seconds: float
+    path_steps: int
+
+
+def monte_carlo(x: np.ndarray, n_paths: int, periods: int, seed: int = 0, first_point: int = 0,
+                tune=None) -> MCResult:
+    """<v> of every row by one batched scan (plan + one graph launch)."""
+    import torch
+    pts = point_workloads(x, n_paths, periods, seed, first_point)
+    mr = [W.to_c(w) for w in pts]
+    t0 = time.perf_counter()
+    sc = B.Scan([m for m, _ in mr], [r for _, r in mr], tune=tune)
+    sc.launch()
+    st = sc.stats()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sc.close()
+    mean = np.array([s.mean for s in st])
+    se = np.array([s.se for s in st])
+    std = np.array([math.sqrt(s.var) if s.n > 1 else float("nan") for s in st])
+    return MCResult(mean, se, std, el, sum(w.path_steps() for w in pts))
+
+
+def train(sur: "B.Surrogate", x: np.ndarray, y: np.ndarray, epochs: int, batch: int = 1024, lr: float = 1e-3,
+          seed: int = 0, lr_final: float = 1e-4):
+    """Minibatch Adam on the mean squared error; member m draws its own minibatches
+    (a bootstrap of the training rows).  Returns the per-epoch mean member loss."""
+    import torch
+    rng = np.random.default_rng(seed)
+    n = len(x)
+    xd = torch.tensor(np.asarray(x, dtype=np.float32), device=sur.device)
+    yd = torch.tensor(np.asarray(y, dtype=np.float32), device=sur.device)
+    boot = rng.integers(0, n, (sur.n, n))
+    steps_per_epoch = max(1, n // batch)
+    total = epochs * steps_per_epoch
+    hist = []
+    k = 0
+    for ep in range(epochs):
+        perm = np.stack([rng.permutation(boot[m]) for m in range(sur.n)])
+        losses = []
+        for s in range(steps_per_epoch):
+            idx = torch.tensor(perm[:, s * batch:(s + 1) * batch].astype(np.int32), device=sur.device)
+            loss = sur.backward(xd, yd, idx)
+            frac = k / max(1, total - 1)
+            sur.adam(lr * (lr_final / lr) ** frac)        # exponential decay to lr_final
+            k += 1
+            if s == steps_per_epoch - 1:
+                losses.append(loss)
+        hist.append(float(torch.stack(losses).mean().item()))
+    return hist
+
+
+@dataclass
+class QueryResult:
+    value: np.ndarray          # surrogate mean, replaced by Monte Carlo where routed
+    std: np.ndarray            # ensemble spread
+    fallback: np.ndarray       # indices answered by Monte Carlo
+    t_query: float
+    t_fallback: float
+
+
+def query(sur: "B.Surrogate", x: np.ndarray, threshold: float, n_paths: int, periods: int,
+          seed: int = 0, mc_first_point: int = 1 << 30) -> QueryResult:
+    import torch
+    xd = torch.tensor(np.asarray(x, dtype=np.float32), device=sur.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mean, std, fidx, fcnt = sur.query(xd, threshold)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n_fb = int(fcnt.item())
+    fb = fidx[:n_fb].cpu().numpy().astype(np.int64)
+    value = mean.cpu().numpy().astype(np.float64)
+    t_fb = 0.0
+    if n_fb:
+        mc = monte_carlo(np.asarray(x)[fb], n_paths, periods, seed, mc_first_point)
+        value[fb] = mc.mean
+        t_fb = mc.seconds
+    return QueryResult(value, std.cpu().numpy(), fb, t1 - t0, t_fb)
