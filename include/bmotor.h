@@ -182,6 +182,13 @@ int bm_reduce(bm_ensemble *e, bm_stats *d_out);
 int bm_read_paths(bm_ensemble *e, uint64_t first, uint64_t count,
                   double *d_x, double *d_v, int64_t *d_noise, double *d_vp);
 
+/* eq. (19): add a histogram of the current folded positions y = x mod L of all
+ * paths to d_counts (n_bins uint64 counters, device; the caller zeroes them):
+ * bin floor(y n_bins / L) of n_bins equal bins of [0, L), computed in FP64.
+ * Calling it at several times between bm_integrate calls accumulates the time
+ * average of the stationary density p(y).  Non-finite positions are skipped. */
+int bm_density(bm_ensemble *e, uint32_t n_bins, uint64_t *d_counts);
+
 /* ------------------------------------------------------------------------- */
 /* Batched parameter scan (Sec. 4, Execution configuration optimizations: the  */
 /* stochastic dynamics solved for many parameter values in one kernel call).   */

@@ -250,3 +250,14 @@ def stats(vp: np.ndarray) -> Stats:
     var = math.fsum(((fin - mean) ** 2).tolist()) / (n - 1) if n > 1 else float("nan")
     se = math.sqrt(var / n) if n > 1 else float("nan")
     return Stats(n=n, n_nonfinite=len(vp) - n, mean=mean, var=var, se=se)
+
+
+def density(params: Params, st: np.ndarray, n_bins: int) -> np.ndarray:
+    """eq. (19): counts of the folded positions y = x mod L in n_bins equal bins of [0, L)."""
+    L = params.period()
+    x = unwrapped(params, st)
+    y = x - L * np.floor(x / L)
+    t = y * n_bins / L
+    ok = np.isfinite(t)
+    b = np.minimum(np.floor(t[ok]).astype(np.int64), n_bins - 1)
+    return np.bincount(b, minlength=n_bins).astype(np.int64)

@@ -81,6 +81,7 @@ SIGNATURES = [
     ("bm_ensemble_steps", ctypes.c_int, [_vp, _P(ctypes.c_uint64)]),
     ("bm_reduce", ctypes.c_int, [_vp, _vp]),
     ("bm_read_paths", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_uint64, _vp, _vp, _vp, _vp]),
+    ("bm_density", ctypes.c_int, [_vp, ctypes.c_uint32, _vp]),
     ("bm_scan_workspace_size", ctypes.c_int, [_P(bm_model), _P(bm_run), _sz, _P(_sz)]),
     ("bm_scan_plan_create", ctypes.c_int, [_P(bm_model), _P(bm_run), _sz, _P(bm_tune), _vp, _sz, _vp, _vp,
                                            _P(_vp)]),
@@ -200,6 +201,10 @@ def bm_reduce(h: int, d_out: int) -> None:
     check(lib().bm_reduce(h, d_out))
 
 
+def bm_density(h: int, n_bins: int, d_counts: int) -> None:
+    check(lib().bm_density(h, n_bins, d_counts))
+
+
 def bm_read_paths(h: int, first: int, count: int, d_x: int | None, d_v: int | None,
                   d_noise: int | None, d_vp: int | None) -> None:
     check(lib().bm_read_paths(h, first, count, d_x, d_v, d_noise, d_vp))
@@ -264,6 +269,11 @@ class Ensemble:
         raw = self.reduce()
         self.stream.synchronize()
         return stats_from_bytes(raw.cpu().numpy().tobytes())
+
+    def density(self, counts):
+        """Add the histogram of the folded positions to the int64 tensor `counts` (eq. 19)."""
+        bm_density(self.h, counts.numel(), counts.data_ptr())
+        return counts
 
     def read(self, first: int = 0, count: int | None = None) -> PathState:
         torch = self.torch

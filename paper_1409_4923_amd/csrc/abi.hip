@@ -468,3 +468,16 @@ extern "C" int bm_read_paths(bm_ensemble *e, uint64_t first, uint64_t count, dou
     if (he != hipSuccess) return hip_fail(he, "export kernel launch");
     return ok();
 }
+
+extern "C" int bm_density(bm_ensemble *e, uint32_t n_bins, uint64_t *d_counts)
+{
+    if (!e) return fail(BM_ERR_INVALID_ARG, "NULL handle");
+    if (!d_counts) return fail(BM_ERR_INVALID_ARG, "d_counts must not be NULL");
+    if (n_bins < 1 || n_bins > (1u << 20)) return fail(BM_ERR_INVALID_ARG, "n_bins must be in [1, 2^20]");
+    const int pot = (int)e->model.pot;
+    hipError_t he = e->run.prec == BM_F32
+                        ? launch_density_f32(pot, e->k, n_bins, (unsigned long long *)d_counts, e->stream)
+                        : launch_density_f64(pot, e->k, n_bins, (unsigned long long *)d_counts, e->stream);
+    if (he != hipSuccess) return hip_fail(he, "density kernel launch");
+    return ok();
+}

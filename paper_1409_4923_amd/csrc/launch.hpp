@@ -24,6 +24,8 @@ BM_DECLARE_LAUNCHERS(f64_in)
 // per-path velocity + wave partials, and the state export (depend on precision and L only)
 hipError_t launch_velocity_f32(int pot, const KArgs &a, hipStream_t s);
 hipError_t launch_velocity_f64(int pot, const KArgs &a, hipStream_t s);
+hipError_t launch_density_f32(int pot, const KArgs &a, uint32_t n_bins, unsigned long long *hist, hipStream_t s);
+hipError_t launch_density_f64(int pot, const KArgs &a, uint32_t n_bins, unsigned long long *hist, hipStream_t s);
 hipError_t launch_read_f32(int pot, const KArgs &a, double *x, double *v, int64_t *nz, double *vp,
                            int with_vp, hipStream_t s);
 hipError_t launch_read_f64(int pot, const KArgs &a, double *x, double *v, int64_t *nz, double *vp,

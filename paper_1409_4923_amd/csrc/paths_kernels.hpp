@@ -354,4 +354,23 @@ __global__ void __launch_bounds__(256) k_read(const KArgs a, double *xo, double 
     }
 }
 
+// ---------------------------------------------------------------------------
+// eq. (19): histogram of the folded positions y = x mod L in n_bins equal bins of
+// [0, L), bin = floor(y n_bins / L), computed in FP64; counts are added to `hist`
+// (integer atomics: the result does not depend on their order).
+// ---------------------------------------------------------------------------
+template <typename R, int POT>
+__global__ void __launch_bounds__(256) k_density(const KArgs a, uint32_t n_bins, unsigned long long *hist)
+{
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.p.n_paths) return;
+    const double L = period<POT>();
+    const double x = (double)arr<R>(a.x)[p];
+    const double y = x - L * floor(x / L);
+    const double t = y * (double)n_bins / L;
+    uint32_t b = t >= (double)n_bins ? n_bins - 1u : (uint32_t)t;   // y rounded up to L
+    if (!(t >= 0.0)) return;                                          // non-finite position
+    atomicAdd(&hist[b], 1ull);
+}
+
 } // namespace bm

@@ -127,6 +127,24 @@ def stratonovich_velocity(U, F: float, D: float, L: float = 1.0, m: int = 8000) 
     return L * J
 
 
+def stratonovich_density(U, F: float, D: float, n_bins: int, L: float = 1.0, m: int = 8000) -> np.ndarray:
+    """Stationary density of x mod L (eq. 19) for x' = -U'(x) + F + sqrt(2D) xi:
+    p(x) proportional to exp(-Phi(x)/D) int_x^{x+L} exp(Phi(y)/D) dy, Phi = U - F x;
+    returned as the probability of each of n_bins equal bins of [0, L)."""
+    w = L / m
+    y = np.arange(2 * m + 1) * w
+    phi = U(y) - F * y
+    shift = np.max(phi) / D
+    cum = integrate.cumulative_trapezoid(np.exp(phi / D - shift), y, initial=0.0)
+    i = np.arange(m + 1)
+    p = np.exp(-phi[i] / D + shift) * (cum[i + m] - cum[i])
+    xs = y[: m + 1]
+    edges = np.linspace(0.0, L, n_bins + 1)
+    cp = integrate.cumulative_trapezoid(p, xs, initial=0.0)
+    cp /= cp[-1]
+    return np.diff(np.interp(edges, xs, cp))
+
+
 # ---------------------------------------------------------------------------
 # Eqs. (21)-(23): currents for the symmetric tent potential (L = 2), D_G = 0.
 # ---------------------------------------------------------------------------

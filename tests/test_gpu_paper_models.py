@@ -1,0 +1,74 @@
+"""The paper's own validation (Sec. 5, Fig. 3) on the GPU: Models I and II with the
+symmetric tent potential (eq. 2, L = 2) at D_G = 0, FP32 paths, 1024 particles,
+10^3 characteristic times, 10% of the run discarded, against the stationary
+velocities of eqs. (21)-(23) (eq. 21b with the sign the dynamics of eqs. 12-14
+produce)."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import closed_forms as cf
+from helpers import say
+from paper_1409_4923_amd import bmotor as B
+from paper_1409_4923_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    B.lib()
+    yield
+
+
+def run_points(ws):
+    mr = [W.to_c(w) for w in ws]
+    sc = B.Scan([m for m, _ in mr], [r for _, r in mr])
+    sc.launch()
+    return sc.stats()
+
+
+@pytest.mark.parametrize("a", [1.5, 2.5])
+def test_fig3a_poisson_model(a):
+    """Model I: spp = 400 steps per 1/lambda, t = 10^3 / lambda."""
+    DPs = [0.25, 0.5, 1.0, 2.0, 4.0]
+    ws = []
+    for i, DP in enumerate(DPs):
+        lam, zeta = a * a / DP, DP / a                   # a = lambda zeta, D_P = lambda zeta^2
+        dt = (1.0 / lam) / 400
+        n = 400 * 1000
+        ws.append(W.Workload(name="fig3a", dyn=W.OVERDAMPED, pot=W.POT_TENT, noise=W.POISSON, prec=W.F32,
+                             lam=lam, zeta=zeta, dt=dt, n_paths=1024, n_steps=n, n_window=n // 10,
+                             seed=31, point=i, x0_lo=0.0, x0_hi=2.0))
+    got = run_points(ws)
+    for DP, g in zip(DPs, got):
+        ref = cf.poisson_tent_velocity(a, DP)
+        say("  a=%.1f D_P=%.2f: MC %.4f +- %.4f   eq.21a %.4f" % (a, DP, g.mean, g.se, ref))
+        assert abs(g.mean - ref) <= 4 * g.se + 0.01 * abs(ref) + 1e-3
+
+
+@pytest.mark.parametrize("Fb", [1.1, 1.6])
+def test_fig3b_dichotomous_model(Fb):
+    """Model II: spp = 200 steps per shorter waiting time, t = 10^3 of it."""
+    Fa = 3.0
+    taus = [0.1, 0.3, 1.0, 3.0]
+    ws = []
+    for i, tau in enumerate(taus):
+        mua, mub = Fa / (tau * (Fa + Fb)), Fb / (tau * (Fa + Fb))
+        tmin = min(1 / mua, 1 / mub)
+        dt = tmin / 200
+        n = 200 * 1000
+        ws.append(W.Workload(name="fig3b", dyn=W.OVERDAMPED, pot=W.POT_TENT, noise=W.DICH, prec=W.F32,
+                             Fa=Fa, Fb=Fb, mua=mua, mub=mub, dt=dt, n_paths=1024, n_steps=n, n_window=n // 10,
+                             seed=32, point=i, x0_lo=0.0, x0_hi=2.0))
+    got = run_points(ws)
+    for tau, g in zip(taus, got):
+        printed = cf.dich_tent_velocity_printed(Fa, Fb, tau)
+        say("  Fb=%.1f tau=%.1f: MC %.4f +- %.4f   -eq.21b %.4f" % (Fb, tau, g.mean, g.se, -printed))
+        assert abs(g.mean + printed) <= 4 * g.se + 0.02 * abs(printed) + 1e-3

@@ -313,3 +313,31 @@ def test_read_range_checked():
     with pytest.raises(B.BMError) as ex:
         e.read(5, 6)
     assert ex.value.code == B.BM_ERR_INVALID_ARG
+
+
+# ---------------------------------------------------------------------------
+# eq. (19): density of the folded positions
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [W.F64, W.F32])
+def test_density_histogram(prec):
+    import torch
+    w = W.C3.with_(prec=prec, n_paths=20000, n_steps=3000, n_window=100)
+    m, r = W.to_c(w)
+    e = B.Ensemble(m, r)
+    counts = torch.zeros(50, dtype=torch.int64, device="cuda")
+    P = to_oracle(w)
+    st = oracle.init(P, 0, w.n_paths)
+    ref = np.zeros(50, dtype=np.int64)
+    n = 0
+    for chunk in (1000, 1000, 1000):
+        e.integrate(chunk)
+        e.density(counts)
+        oracle.advance(P, st, 0, n, n + chunk, threads=ORACLE_THREADS)
+        n += chunk
+        ref += oracle.density(P, st, 50)
+    got = counts.cpu().numpy()
+    assert got.sum() == 3 * w.n_paths
+    if prec == W.F64:
+        assert np.array_equal(got, ref)
+    else:
+        assert np.max(np.abs(got - ref)) <= 0.02 * ref.max() + 20

@@ -503,3 +503,24 @@ def test_initial_conditions(orc):
     # d is set opposite to the stationary draw; Pr{d* = +Fb} = mua/(mua+mub)
     assert abs(np.mean(st["d"] == 0) - 1 / 3) < 4 * math.sqrt(2 / 9 / N)
     assert np.all(st["sD"] == 0)
+
+
+@pytest.mark.slow
+def test_stationary_density_tilted_washboard(orc):
+    """eq. (19): the time-averaged histogram of x mod L approaches the stationary
+    density of the tilted washboard, p ~ exp(-Phi/D) int_x^{x+L} exp(Phi/D)."""
+    F, D, nb = 2.0, 0.5, 20
+    P = orc.Params(pot=orc.POT_SIN, noise=orc.GAUSS, F=F, D=D, dt=2e-3)
+    st = orc.init(P, 0, 4096)
+    orc.advance(P, st, 0, 0, 2000, threads=THREADS)          # burn-in, t = 4
+    counts = np.zeros(nb, dtype=np.int64)
+    n = 2000
+    for k in range(20):
+        orc.advance(P, st, 0, n, n + 250, threads=THREADS)
+        n += 250
+        counts += orc.density(P, st, nb)
+    expect = cf.stratonovich_density(lambda x: np.sin(TWO_PI * x), F, D, nb) * counts.sum()
+    # samples 0.5 time units apart are correlated: compare with a generous chi-square
+    chi2 = np.sum((counts - expect) ** 2 / expect)
+    assert chi2 / nb < 4.0, (chi2, counts, expect)
+    assert np.max(np.abs(counts / expect - 1)) < 0.05
