@@ -28,7 +28,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 OVERDAMPED, INERTIAL = 0, 1
 POT_SIN, POT_RATCHET, POT_TENT, POT_FREE, POT_HARMONIC = 0, 1, 2, 3, 4
-GAUSS, POISSON, DICH = 1, 2, 4
+GAUSS, POISSON, DICH, NORMAL = 1, 2, 4, 8
 
 
 def build(force: bool = True) -> str:
@@ -76,6 +76,8 @@ def lib():
         L.or_philox4x64_10.argtypes = [u64p, u64p, u64p]
         L.or_three_point.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint64, ctypes.c_int64]
         L.or_three_point.restype = ctypes.c_int
+        L.or_normal.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint64, ctypes.c_int64]
+        L.or_normal.restype = ctypes.c_double
         L.or_init.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
         L.or_advance.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint64, ctypes.c_uint64,
                                  ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]
@@ -98,7 +100,8 @@ class Params:
     dyn: OVERDAMPED (eq. 24) or INERTIAL (x'' + gamma x' = ...).
     pot: POT_SIN (V = sin 2 pi x), POT_RATCHET (V = -sin 2 pi x - sin(4 pi x)/4),
          POT_TENT (eq. 2, L = 2), POT_FREE, POT_HARMONIC (V = k x^2 / 2).
-    noise: bit mask of GAUSS | POISSON | DICH.
+    noise: bit mask of GAUSS | POISSON | DICH (NORMAL: Gaussian noise with normal
+           increments instead of the three-point ones).
     Poisson (eqs. 3-6): lam, zeta.  Dichotomous (eqs. 13-14): levels -Fa / +Fb,
     leaving rates mua (of -Fa) and mub (of +Fb).
     spp > 0: dt = (2 pi / omega) / spp unless dt is given; drive phase = n mod spp.
@@ -171,6 +174,12 @@ def three_point(params: Params, path: int, n: int) -> int:
     """Sign (-1, +1, 0) of the Algorithm 2 increment of `path` at step n."""
     cp = params.c()
     return int(lib().or_three_point(ctypes.byref(cp), path, n))
+
+
+def normal(params: Params, path: int, n: int) -> float:
+    """Standard normal variate of `path` at step n (non-simplified scheme)."""
+    cp = params.c()
+    return float(lib().or_normal(ctypes.byref(cp), path, n))
 
 
 def init(params: Params, first_path: int, count: int) -> np.ndarray:

@@ -13,7 +13,8 @@
  *   - counter-based random numbers: Philox4x32-10 / Philox4x64-10
  *     (Salmon, Moraes, Dror & Shaw, SC'11, "Parallel random numbers: as easy
  *     as 1, 2, 3"), restated from that paper's definition;
- *   - Algorithm 2 / eq. (25): three-point Gaussian increment;
+ *   - Algorithm 2 / eq. (25): three-point Gaussian increment (and, for
+ *     comparison, the normal increments it replaces);
  *   - Algorithm 3 / eqs. (3)-(6), (26)-(27): white Poissonian increment;
  *   - Algorithm 4 / eqs. (13)-(14), (29)-(30): dichotomous increment;
  *   - Algorithm 1: predictor-corrector step for eq. (24) (and the inertial
@@ -120,7 +121,8 @@ enum { OR_POT_SIN = 0,      /* V = sin(2 pi x), L = 1                    */
        OR_POT_TENT = 2,     /* eq. (2): V = 1+x on [-1,0), 1-x on [0,1], L = 2 */
        OR_POT_FREE = 3,     /* V = 0 (test potential), L = 1             */
        OR_POT_HARMONIC = 4  /* V = k x^2/2 (test potential), no folding  */ };
-enum { OR_GAUSS = 1, OR_POISSON = 2, OR_DICH = 4 };
+enum { OR_GAUSS = 1, OR_POISSON = 2, OR_DICH = 4,
+       OR_NORMAL = 8   /* Gaussian noise with normal increments (non-simplified scheme) */ };
 
 typedef struct {
     int32_t dyn, pot, noise, literal_alg1;
@@ -191,6 +193,24 @@ int or_three_point(const or_params *P, uint64_t path, int64_t n)
     if (digit == 0) return -1;      /* phi <= 1/6          */
     if (digit == 1) return +1;      /* 1/6 < phi <= 1/3    */
     return 0;                       /* otherwise           */
+}
+
+/* ------------------------------------------------------------------------ */
+/* Non-simplified scheme (the Gaussian increments that eq. (25) replaces):   */
+/* Delta xi ~ N(0, G^2 dt).  Standard normal z at step n by the Box-Muller   */
+/* transform of words (2j, 2j+1) of block n/4, j = (n mod 4)/2:              */
+/*   r = sqrt(-2 ln(1 - phi_1)), z = r cos(2 pi phi_2) (n even),             */
+/*   z = r sin(2 pi phi_2) (n odd),  phi = w 2^-32.                          */
+/* ------------------------------------------------------------------------ */
+double or_normal(const or_params *P, uint64_t path, int64_t n)
+{
+    uint32_t w[4];
+    draw(P, (uint32_t)(n / 4), path, 0u, w);
+    int j = (int)((n % 4) / 2);
+    double phi1 = (double)w[2 * j] * 0x1p-32;
+    double phi2 = (double)w[2 * j + 1] * 0x1p-32;
+    double r = sqrt(-2.0 * log(1.0 - phi1));
+    return (n % 2 == 0) ? r * cos(2.0 * PI * phi2) : r * sin(2.0 * PI * phi2);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -288,6 +308,9 @@ static void step(const or_params *P, uint64_t path, int64_t n, or_path *s)
     if (P->noise & OR_GAUSS) {
         double G = (P->dyn == OR_INERTIAL) ? sqrt(2.0 * P->gamma * P->D) : sqrt(2.0 * P->D);
         dxi = (double)or_three_point(P, path, n) * G * sqrt(3.0 * h);
+    } else if (P->noise & OR_NORMAL) {
+        double G = (P->dyn == OR_INERTIAL) ? sqrt(2.0 * P->gamma * P->D) : sqrt(2.0 * P->D);
+        dxi = or_normal(P, path, n) * G * sqrt(h);
     }
 
     /* Algorithm 3: Poissonian increment (kick amplitude z; bias a = lambda zeta). */

@@ -524,3 +524,42 @@ def test_stationary_density_tilted_washboard(orc):
     chi2 = np.sum((counts - expect) ** 2 / expect)
     assert chi2 / nb < 4.0, (chi2, counts, expect)
     assert np.max(np.abs(counts / expect - 1)) < 0.05
+
+
+# ---------------------------------------------------------------------------
+# Non-simplified scheme: normal increments
+# ---------------------------------------------------------------------------
+def test_normal_increments_distribution(orc):
+    P = orc.Params(seed=21, dt=0.01)
+    z = np.array([orc.normal(P, p, n) for p in range(100) for n in range(200)])
+    assert sps.kstest(z, "norm").pvalue > 1e-3
+    assert abs(z.mean()) < 4 / math.sqrt(len(z))
+    # Box-Muller pairs: steps 2j and 2j+1 share the radius
+    r2 = np.array([orc.normal(P, 7, 2 * j) ** 2 + orc.normal(P, 7, 2 * j + 1) ** 2 for j in range(2000)])
+    assert sps.kstest(r2 / 2.0, "expon").pvalue > 1e-3      # r^2 / 2 ~ Exp(1)
+
+
+def test_ou_recurrence_with_normal_increments(orc):
+    """Same linear recurrence of Algorithm 1, now with Delta xi = G sqrt(dt) z."""
+    P = orc.Params(pot=orc.POT_HARMONIC, k_harm=1.5, noise=orc.NORMAL, D=0.4, dt=0.03,
+                   x0_lo=-1.0, x0_hi=1.0)
+    R, c = cf.pc_linear_coeffs(1.5 * 0.03)
+    g = math.sqrt(2 * P.D) * math.sqrt(P.dt)
+    st0 = orc.init(P, 0, 8)
+    st = orc.advance(P, st0.copy(), 0, 0, 300)
+    for p in range(8):
+        x = st0["x"][p]
+        for n in range(300):
+            x = R * x + c * g * orc.normal(P, p, n)
+        assert abs(st["x"][p] - x) < 1e-12
+
+
+def test_free_diffusion_normal_increments(orc):
+    P = orc.Params(pot=orc.POT_FREE, noise=orc.NORMAL, D=0.25, dt=0.02)
+    n, N = 200, 8192
+    st0 = orc.init(P, 0, N)
+    x0 = orc.unwrapped(P, st0)
+    st = orc.advance(P, st0.copy(), 0, 0, n, threads=THREADS)
+    dx = orc.unwrapped(P, st) - x0
+    # a sum of normals is normal with variance 2 D t
+    assert sps.kstest(dx / math.sqrt(2 * P.D * n * P.dt), "norm").pvalue > 1e-3
