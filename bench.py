@@ -23,38 +23,56 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published figures: 256 CUs, 2.4 GHz; 64 VALU lanes per CU per clock.
+# MI355X published figures: 256 CUs, 2.4 GHz.  Each CU has 4 SIMDs of 16 lanes,
+# so the main VALU pipe retires 64 lane-instructions per CU per clock (one wave64
+# instruction per CU-clock); transcendental instructions (cos, log, exp, sqrt, rcp)
+# go to a separate unit that runs alongside it.  The published FP32 vector peak
+# (157.3 TFLOP/s) needs packed FP32 FMAs (2 elements x 2 flops per lane-clock),
+# which this library does not emit; FP64 FMAs run at the same lane rate.
 N_CU, CLOCK_HZ, LANES_PER_CU = 256, 2.4e9, 64
-VALU_LANE_OPS_PEAK = N_CU * LANES_PER_CU * CLOCK_HZ          # 3.93e13 lane-ops/s
+VALU_LANE_OPS_PEAK = N_CU * LANES_PER_CU * CLOCK_HZ          # 3.93e13 lane-instr/s
 FP32_PEAK_FLOPS = 157.3e12                                   # packed FP32 vector
 FP64_PEAK_FLOPS = 78.6e12
 
+# HBM traffic of k_advance on the default workload from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE), averaged over the two launches of one step and
+# scaled by what the same counters read for a 1 GiB device copy (FETCH_SIZE
+# reads 0.5 GiB for it: factor 2.0; WRITE_SIZE reads 1 GiB: factor 1.0).  Valid
+# only while the integration kernel's sources hash to KERNEL_SOURCES_SHA256.
+TRAFFIC_WORKLOAD = "inertial-poisson-f32-2^20"
+TRAFFIC_BYTES_PER_LAUNCH = ((10990.0625 + 10497.5) / 2 * 2.0 + (28672.0 + 20480.0) / 2 * 1.0) * 1024
+KERNEL_SOURCES = ("common.hpp", "paths.hpp", "paths_kernels.hpp", "paths_tu.inc", "paths_f32_in.hip",
+                  "launch.hpp")
+KERNEL_SOURCES_SHA256 = "5576f54df932629b9d0d672e0162be676b84135afc56e543e3a7b4b695b0b1e9"
+
 
 def algorithmic_work(w):
-    """(VALU lane-ops, FP32/FP64 flops) the method needs per path-step.
+    """(VALU lane-ops, transcendental lane-ops, flops) the method needs per path-step.
 
     Counted from Algorithms 1-4 in their cheapest direct form, one op per add,
-    multiply, FMA, compare, select, conversion or transcendental; flops count an
-    FMA as 2 and a transcendental as 1.  Philox4x32-10 = 10 rounds x (2 wide
-    products + 2 three-way xors) = 40 ops, amortised over 16 steps (Algorithm 2)
-    or 2 kicks / 4 flips (Algorithms 3 / 4).
+    multiply, FMA, compare, select or conversion; transcendentals (cos, log) are
+    counted apart because they issue to their own unit.  Flops count an FMA as 2
+    and a transcendental as 1.  Philox4x32-10 = 10 rounds x (2 wide products + 2
+    three-way xors) = 40 ops, amortised over 16 steps (Algorithm 2) or 2 kicks /
+    4 flips (Algorithms 3 / 4).
     """
     from paper_1409_4923_amd import workloads as W
-    ops = flops = 0.0
+    ops = trans = flops = 0.0
     inertial = w.dyn == W.INERTIAL
     # drift evaluations (3 per step): potential force + drive + friction
     if w.pot == W.POT_SIN:
-        per_eval_ops, per_eval_flops = 2, 3            # cos, fma(-2 pi, c, A')
+        per_eval_ops, per_eval_trans, per_eval_flops = 1, 1, 3     # cos | fma(-2 pi, c, A')
     elif w.pot == W.POT_RATCHET:
-        per_eval_ops, per_eval_flops = 4, 5            # cos, add, mul, fma
+        per_eval_ops, per_eval_trans, per_eval_flops = 3, 1, 5     # cos | add, mul, fma
     elif w.pot == W.POT_TENT:
-        per_eval_ops, per_eval_flops = 4, 2            # mul, floor, fma, cmp/select
+        per_eval_ops, per_eval_trans, per_eval_flops = 4, 0, 2     # mul, floor, fma, cmp/select
     else:
-        per_eval_ops, per_eval_flops = 0, 0
+        per_eval_ops, per_eval_trans, per_eval_flops = 0, 0, 0
     if inertial:
-        per_eval_ops += 1                             # fma(-gamma, v, f)
+        per_eval_ops += 1                                        # fma(-gamma, v, f)
         per_eval_flops += 2
     ops += 3 * per_eval_ops
+    trans += 3 * per_eval_trans
     flops += 3 * per_eval_flops
     # constant-within-step forcing A' = A(t) + level - bias at t_n and t_{n+1}
     if w.noise & (W.POISSON | W.DICH):
@@ -74,11 +92,25 @@ def algorithmic_work(w):
         ops += 5 + 40.0 / 16.0                        # 2 compares, 2 selects, digit shift
     p_kick = -math.expm1(-w.lam * w.step()) if (w.noise & W.POISSON) else 0.0
     if w.noise & W.POISSON:
-        ops += 2 + p_kick * (40.0 / 2.0 + 10.0)       # countdown; kick: draws, 2 logs, floor
+        ops += 2 + p_kick * (40.0 / 2.0 + 8.0)        # countdown; kick: draws, floor, scaling
+        trans += p_kick * 2.0                         # two logs per kick
+        flops += p_kick * 2.0
     if w.noise & W.DICH:
         p_flip = max(-math.expm1(-w.mua * w.step()), -math.expm1(-w.mub * w.step()))
-        ops += 3 + p_flip * (40.0 / 4.0 + 6.0)        # countdown + level select; flip draw
-    return ops, flops
+        ops += 3 + p_flip * (40.0 / 4.0 + 5.0)        # countdown + level select; flip draw
+        trans += p_flip                               # one log per flip
+        flops += p_flip
+    flops += 3 * per_eval_trans
+    return ops, trans, flops
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1409_4923_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def oracle_baseline(w, seconds: float, threads: int):
@@ -131,7 +163,7 @@ def scan_leg(args):
     sec = e0.elapsed_time(e1) / 1e3
     st = B.stats_array_from_bytes(res.cpu().numpy().tobytes(), len(pts))
     total = sum(w.path_steps() for w in pts)
-    ops, _ = algorithmic_work(pts[0])
+    ops, _, _ = algorithmic_work(pts[0])
     print("scan leg: %.3g path-steps in %.3f s" % (total, sec), file=sys.stderr, flush=True)
     return {"workload": "inertial-scan-4096-points", "n_points": len(pts), "path_steps": total,
             "seconds": sec, "path_steps_per_s": total / sec, "points_per_s": len(pts) / sec,
@@ -239,7 +271,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(paths and parameter points shard trivially; see the design notes).", file=sys.stderr)
+              "(paths and parameter points would shard across GPUs by index range).", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -290,8 +322,11 @@ def main():
     launches = 2 if 0 < w.n_window < w.n_steps else 1
     ps_per_step = w.path_steps()
     value = ps_per_step * args.steps / (t1 - t0)
-    ops, flops = algorithmic_work(w)
+    ops, trans, flops = algorithmic_work(w)
     achieved = ops * ps_per_step / int_s
+    traffic = None
+    if w.name == TRAFFIC_WORKLOAD and kernel_sources_sha256() == KERNEL_SOURCES_SHA256:
+        traffic = TRAFFIC_BYTES_PER_LAUNCH
     peak_flops = FP32_PEAK_FLOPS if w.prec == W.F32 else FP64_PEAK_FLOPS
     rec = {
         "metric": "path-steps/s",
@@ -317,8 +352,10 @@ def main():
             "peak": VALU_LANE_OPS_PEAK / 1e12,
             "unit": "TOP/s (VALU lane-ops)",
             "frac": achieved / VALU_LANE_OPS_PEAK,
-            "traffic": None,
+            "traffic": traffic,
             "ops_per_path_step": ops,
+            "trans_ops_per_path_step": trans,
+            "path_steps_per_launch": ps_per_step / launches,
             "kernel_ms_per_launch": int_s * 1e3 / launches,
             "launches_per_step": launches,
             "fp32_flops": {"achieved_tflops": flops * ps_per_step / int_s / 1e12,
