@@ -1,0 +1,69 @@
+"""What the learned surrogate gains over plain Monte Carlo (GPU).
+
+Labels come from one batched scan; the 5-member ensemble is trained on the GPU by
+the library's own backward / Adam kernels; held-out truth comes from a scan with
+4x the paths.  Plain-MC cost of a point at |d<v>| <= 0.01 is the path-steps needed
+for 3 SE <= 0.01 at the measured scan throughput; the surrogate's cost is its
+query time plus that MC cost for the routed queries.  The sub-domain (D >= 10^-1.5,
+a <= 1) is one where <v> is smooth, so the ensemble agrees and is right.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from helpers import say
+from paper_1409_4923_amd import bmotor as B
+from paper_1409_4923_amd import surrogate as S
+from paper_1409_4923_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    B.lib()
+    yield
+
+
+def smooth_queries(n, seed):
+    x = W.surrogate_queries(n, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    x[:, 0] = rng.uniform(0.0, 1.0, n)
+    x[:, 3] = 10.0 ** rng.uniform(-1.5, -1.0, n)
+    return x.astype(np.float32)
+
+
+def test_surrogate_gain_over_monte_carlo():
+    import torch
+    tol, thr = 0.01, 0.005
+    xl = smooth_queries(20000, 5)
+    lab = S.monte_carlo(xl, 1024, 100, seed=1)
+    say("labels: 20000 points in %.2f s, median SE %.4f" % (lab.seconds, np.median(lab.se)))
+    sur = B.Surrogate(5, seed=3)
+    hist = S.train(sur, xl, lab.mean, epochs=30, batch=1024, lr=2e-3, seed=4)
+    say("train loss %.3g -> %.3g" % (hist[0], hist[-1]))
+    assert hist[-1] < 0.1 * hist[0]
+    xh = smooth_queries(1000, 9)
+    truth = S.monte_carlo(xh, 4096, 100, seed=2, first_point=1 << 24)
+    mean, std, fidx, fcnt = sur.query(torch.tensor(xh, device="cuda"), thr)
+    mean, std = mean.cpu().numpy(), std.cpu().numpy()
+    keep = std <= thr
+    err = np.abs(mean - truth.mean)
+    say("answered %d of 1000, p95 |err| %.4f (truth SE median %.4f)"
+        % (keep.sum(), np.percentile(err[keep], 95) if keep.any() else -1, np.median(truth.se)))
+    assert keep.mean() > 0.5
+    assert np.percentile(err[keep], 95) <= tol
+    # points/s at |d<v>| <= tol
+    rate = truth.path_steps / truth.seconds
+    need = np.maximum(64.0, np.ceil((3.0 * truth.std / tol) ** 2))
+    mc_cost = float(np.mean(need) * 100 * S.SPP / rate)
+    q = S.query(sur, smooth_queries(100_000, 11), thr, n_paths=4096, periods=100, seed=3)
+    f = len(q.fallback) / 100_000
+    sur_rate = 100_000 / (q.t_query + f * 100_000 * mc_cost)
+    say("MC %.1f points/s, surrogate %.1f points/s (fallback %.3f), gain %.1f"
+        % (1 / mc_cost, sur_rate, f, sur_rate * mc_cost))
+    assert sur_rate * mc_cost > 10.0
