@@ -71,6 +71,12 @@ extern "C" {
 #define BM_NOISE_GAUSS   1u  /* xi: Gaussian white noise, Algorithm 2                       */
 #define BM_NOISE_POISSON 2u  /* eta: white Poissonian noise, Algorithm 3                    */
 #define BM_NOISE_DICH    4u  /* Gamma: dichotomous noise, Algorithm 4                       */
+/* xi integrated with normal increments N(0, G^2 dt) instead of eq. (25)'s three-point
+ * law: the non-simplified scheme, for comparison (Sec. 3).  The standard normal of
+ * step n is the Box-Muller transform of words (2j, 2j+1), j = (n mod 4)/2, of the
+ * Philox block (n/4, path, point, tag 0): cos for even n, sin for odd n.  Excludes
+ * BM_NOISE_GAUSS; ensembles only (bm_scan rejects it with BM_ERR_UNSUPPORTED). */
+#define BM_NOISE_NORMAL  8u
 
 /* bm_run.prec: arithmetic of the path state (statistics are always FP64) */
 #define BM_F64 0u

@@ -24,7 +24,7 @@ BM_ERR_STATE = -5
 
 BM_OVERDAMPED, BM_INERTIAL = 0, 1
 BM_POT_SIN, BM_POT_RATCHET, BM_POT_TENT, BM_POT_FREE = 0, 1, 2, 3
-BM_NOISE_GAUSS, BM_NOISE_POISSON, BM_NOISE_DICH = 1, 2, 4
+BM_NOISE_GAUSS, BM_NOISE_POISSON, BM_NOISE_DICH, BM_NOISE_NORMAL = 1, 2, 4, 8
 BM_F64, BM_F32 = 0, 1
 
 
@@ -475,6 +475,9 @@ class Surrogate:
         return y
 
     def backward(self, x, t, idx=None):
+        if idx is not None and (not idx.is_contiguous() or idx.dtype != self.torch.int32
+                                or idx.dim() != 2 or idx.shape[0] != self.n):
+            raise ValueError("idx must be a contiguous int32 tensor [n_members, batch]")
         B = idx.shape[1] if idx is not None else x.shape[0]
         loss = self.torch.empty(self.n, dtype=self.torch.float32, device=self.device)
         ws, nb = self._workspace(B, True)

@@ -67,7 +67,9 @@ int validate(const bm_model *m, const bm_run *r)
     if (r->size != sizeof(bm_run)) return fail(BM_ERR_INVALID_ARG, "bm_run.size mismatch");
     if (m->dyn > BM_INERTIAL) return fail(BM_ERR_INVALID_ARG, "unknown dynamics %u", m->dyn);
     if (m->pot > BM_POT_FREE) return fail(BM_ERR_INVALID_ARG, "unknown potential %u", m->pot);
-    if (m->noise & ~7u) return fail(BM_ERR_INVALID_ARG, "unknown noise bits 0x%x", m->noise);
+    if (m->noise & ~15u) return fail(BM_ERR_INVALID_ARG, "unknown noise bits 0x%x", m->noise);
+    if ((m->noise & BM_NOISE_GAUSS) && (m->noise & BM_NOISE_NORMAL))
+        return fail(BM_ERR_INVALID_ARG, "BM_NOISE_GAUSS and BM_NOISE_NORMAL are alternatives");
     if (r->prec > BM_F32) return fail(BM_ERR_INVALID_ARG, "unknown precision %u", r->prec);
     if (m->dyn == BM_INERTIAL && !(fin(m->gamma) && m->gamma > 0))
         return fail(BM_ERR_INVALID_ARG, "gamma must be finite and > 0");
@@ -84,7 +86,7 @@ int validate(const bm_model *m, const bm_run *r)
         if (!(fin(r->dt) && r->dt > 0)) return fail(BM_ERR_INVALID_ARG, "dt must be finite and > 0");
         dt = r->dt;
     }
-    if (m->noise & BM_NOISE_GAUSS)
+    if (m->noise & (BM_NOISE_GAUSS | BM_NOISE_NORMAL))
         if (!(fin(m->D) && m->D >= 0)) return fail(BM_ERR_INVALID_ARG, "D must be finite and >= 0");
     if (m->noise & BM_NOISE_POISSON) {
         if (!(fin(m->shot_rate) && m->shot_rate > 0))
@@ -253,6 +255,10 @@ PointConst point_const(const bm_model *m, const bm_run *r, const void *d_tab)
     if (m->noise & BM_NOISE_GAUSS) {
         const double G = m->dyn == BM_INERTIAL ? std::sqrt(2.0 * m->gamma * m->D) : std::sqrt(2.0 * m->D);
         k.g3 = G * std::sqrt(3.0 * h);
+    }
+    if (m->noise & BM_NOISE_NORMAL) {           // scale of a standard normal: G sqrt(dt)
+        const double G = m->dyn == BM_INERTIAL ? std::sqrt(2.0 * m->gamma * m->D) : std::sqrt(2.0 * m->D);
+        k.g3 = G * std::sqrt(h);
     }
     // FP32 countdown estimates: error < 3e-7 / (rate dt) + 4.2e-7 X (rounding of
     // 1 - phi, v_log_f32 near 1, the scale); the tolerance is about 7x / 10x that.

@@ -103,7 +103,7 @@ struct PointConst {
     uint64_t n_steps;     // horizon (scan)
     uint64_t n_window;    // eq. (31): step index of t_i
     double dt, gamma;
-    double g3;            // G sqrt(3 dt)
+    double g3;            // G sqrt(3 dt) (three-point), G sqrt(dt) (normal increments)
     double lam_dt;        // lambda dt
     double zeta;
     double Fa, Fb;

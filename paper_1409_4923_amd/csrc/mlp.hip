@@ -94,21 +94,86 @@ __global__ void k_loss_final(const float *partial, int nblk, int B, float *loss)
     loss[m] = s / (float)B;
 }
 
-// Layer 4 backward: dW4, db4 (one block per member, lane = input), and
-// dz3 = dy W4 gelu'(z3) (grid (B, members)).
-__global__ void __launch_bounds__(256) k_l4_bwd_w(const float *dy, const bf16_t *a3, int B, float *grad)
+// Gradients that are column sums over the batch rather than GEMMs: the biases
+// (db = sum_b dz[b][:]), the 1-wide output layer (dW4 = sum_b dy[b] a3[b][:],
+// db4 = sum_b dy[b]) and the 5-wide input layer (dW1[o][j] = sum_b dz1[b][o] u[b][j],
+// db1 = sum_b dz1[b][:]).  Pass 1: grid (n_chunks, members), lane = column o, each
+// block sums one chunk of consecutive rows; pass 2 adds the chunks in order, so the
+// result does not depend on the launch.
+enum { RED_BIAS = 0, RED_L4 = 1, RED_L1 = 2 };
+
+template <int KIND>
+struct RedWidth { static constexpr int value = KIND == RED_BIAS ? 1 : KIND == RED_L4 ? 2 : IN + 1; };
+
+constexpr int RED_MAX_CHUNKS = 64;
+
+__host__ __device__ inline int red_rows(int B) { return B / 64 < 16 ? 16 : B / 64; }
+
+template <int KIND>
+__global__ void __launch_bounds__(256) k_colsum(const bf16_t *dz, const float *dy, const bf16_t *a3,
+                                                const float *u, int B, int rows, float *part)
 {
-    const int m = blockIdx.y, i = threadIdx.x;
-    float s = 0.0f, sb = 0.0f;
-    for (int b = 0; b < B; ++b) {
-        const float d = dy[(uint64_t)m * B + b];
-        s = fmaf(d, bf2f(a3[((uint64_t)m * B + b) * H + i]), s);
-        sb += d;
+    constexpr int NV = RedWidth<KIND>::value;
+    const int c = blockIdx.x, m = blockIdx.y, o = threadIdx.x, nchunk = gridDim.x;
+    float s[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) s[q] = 0.0f;
+    const uint64_t row0 = (uint64_t)m * B + (uint64_t)c * rows;
+    for (int r = 0; r < rows; ++r) {
+        const uint64_t row = row0 + r;
+        if constexpr (KIND == RED_BIAS) {
+            s[0] += bf2f(dz[row * H + o]);
+        } else if constexpr (KIND == RED_L4) {
+            const float d = dy[row];
+            s[0] = fmaf(d, bf2f(a3[row * H + o]), s[0]);
+            s[1] += d;
+        } else {
+            const float d = bf2f(dz[row * H + o]);
+#pragma unroll
+            for (int j = 0; j < IN; ++j) s[j] = fmaf(d, u[row * IN + j], s[j]);
+            s[IN] += d;
+        }
     }
-    grad[(uint64_t)m * NPARAM + OFF_W4 + i] = s;
-    if (i == 0) grad[(uint64_t)m * NPARAM + OFF_B4] = sb;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) part[(((uint64_t)m * nchunk + c) * NV + q) * H + o] = s[q];
 }
 
+template <int KIND>
+__global__ void __launch_bounds__(256) k_colsum_final(const float *part, int nchunk, float *grad, int off)
+{
+    constexpr int NV = RedWidth<KIND>::value;
+    const int m = blockIdx.x, o = threadIdx.x;
+    float s[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) s[q] = 0.0f;
+    for (int c = 0; c < nchunk; ++c) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) s[q] += part[(((uint64_t)m * nchunk + c) * NV + q) * H + o];
+    }
+    float *g = grad + (uint64_t)m * NPARAM;
+    if constexpr (KIND == RED_BIAS) {
+        g[off + o] = s[0];
+    } else if constexpr (KIND == RED_L4) {
+        g[OFF_W4 + o] = s[0];
+        if (o == 0) g[OFF_B4] = s[1];
+    } else {
+#pragma unroll
+        for (int j = 0; j < IN; ++j) g[OFF_W1 + o * IN + j] = s[j];
+        g[OFF_B1 + o] = s[IN];
+    }
+}
+
+template <int KIND>
+hipError_t colsum(uint32_t nm, int B, const bf16_t *dz, const float *dy, const bf16_t *a3, const float *u,
+                  float *part, float *grad, int off, hipStream_t s)
+{
+    const int rows = red_rows(B), nchunk = B / rows;
+    hipLaunchKernelGGL(k_colsum<KIND>, dim3(nchunk, nm), dim3(256), 0, s, dz, dy, a3, u, B, rows, part);
+    hipLaunchKernelGGL(k_colsum_final<KIND>, dim3(nm), dim3(256), 0, s, (const float *)part, nchunk, grad, off);
+    return hipGetLastError();
+}
+
+// dz3 = dy W4 gelu'(z3), grid (B, members), lane = column.
 __global__ void __launch_bounds__(256) k_l4_bwd_dz(const float *dy, const bf16_t *wbf, const float *z3, int B,
                                                    bf16_t *dz3)
 {
@@ -116,32 +181,6 @@ __global__ void __launch_bounds__(256) k_l4_bwd_dz(const float *dy, const bf16_t
     const uint64_t row = (uint64_t)m * B + b;
     const float w = bf2f(wbf[(uint64_t)m * NBF + BOFF_W4 + i]);
     dz3[row * H + i] = f2bf(dy[row] * w * gelu_grad(z3[row * H + i]));
-}
-
-// Bias gradient db[o] = sum_b dz[b][o]; one block per member, lane = o.
-__global__ void __launch_bounds__(256) k_bias_grad(const bf16_t *dz, int B, float *grad, int off)
-{
-    const int m = blockIdx.y, o = threadIdx.x;
-    float s = 0.0f;
-    for (int b = 0; b < B; ++b) s += bf2f(dz[((uint64_t)m * B + b) * H + o]);
-    grad[(uint64_t)m * NPARAM + off + o] = s;
-}
-
-// Layer 1 weights: dW1[o][j] = sum_b dz1[b][o] u[b][j], db1[o] = sum_b dz1[b][o].
-__global__ void __launch_bounds__(256) k_l1_bwd(const bf16_t *dz1, const float *u, int B, float *grad)
-{
-    const int m = blockIdx.y, o = threadIdx.x;
-    float s[IN] = {0.f, 0.f, 0.f, 0.f, 0.f}, sb = 0.0f;
-    for (int b = 0; b < B; ++b) {
-        const uint64_t row = (uint64_t)m * B + b;
-        const float d = bf2f(dz1[row * H + o]);
-        sb += d;
-#pragma unroll
-        for (int j = 0; j < IN; ++j) s[j] = fmaf(d, u[row * IN + j], s[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < IN; ++j) grad[(uint64_t)m * NPARAM + OFF_W1 + o * IN + j] = s[j];
-    grad[(uint64_t)m * NPARAM + OFF_B1 + o] = sb;
 }
 
 // BF16 index of parameter p of a member, or -1 for biases.
@@ -266,7 +305,7 @@ __global__ void __launch_bounds__(256) k_compact(const float *stdv, uint64_t B, 
 size_t up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct MlpLayout {
-    size_t u, z1, z2, z3, a1, a2, a3, y, dy, dz1, dz2, dz3, part, mean, stdv, blk, total;
+    size_t u, z1, z2, z3, a1, a2, a3, y, dy, dz1, dz2, dz3, part, red, mean, stdv, blk, total;
     uint64_t rows;    // rows per pass
 };
 
@@ -291,6 +330,7 @@ MlpLayout mlp_layout(uint32_t nm, uint64_t batch, bool training)
         L.dz2 = take(nm * R * H * 2);
         L.dz3 = take(nm * R * H * 2);
         L.part = take(nm * ((R + 255) / 256) * 4);
+        L.red = take((size_t)nm * RED_MAX_CHUNKS * (IN + 1) * H * 4);
     } else {
         L.blk = take(((batch + 255) / 256) * 4 + 4);
     }
@@ -455,7 +495,7 @@ extern "C" int bm_mlp_backward(uint32_t n_members, const float *d_params, const 
     float *z1 = (float *)(ws + L.z1), *z2 = (float *)(ws + L.z2), *z3 = (float *)(ws + L.z3);
     bf16_t *a1 = (bf16_t *)(ws + L.a1), *a2 = (bf16_t *)(ws + L.a2), *a3 = (bf16_t *)(ws + L.a3);
     bf16_t *dz1 = (bf16_t *)(ws + L.dz1), *dz2 = (bf16_t *)(ws + L.dz2), *dz3 = (bf16_t *)(ws + L.dz3);
-    float *part = (float *)(ws + L.part);
+    float *part = (float *)(ws + L.part), *red = (float *)(ws + L.red);
 
     hipError_t e = forward_pass(nm, d_params, wbf, d_x, d_idx, batch, 0, B, ws, L, true, y, batch, 0, s);
     const int nblk = (B + 255) / 256;
@@ -468,9 +508,11 @@ extern "C" int bm_mlp_backward(uint32_t n_members, const float *d_params, const 
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_l4_bwd_w, dim3(1, nm), dim3(256), 0, s, dy, a3, B, d_grad);
-        hipLaunchKernelGGL(k_l4_bwd_dz, dim3(B, nm), dim3(256), 0, s, dy, wbf, z3, B, dz3);
-        e = hipGetLastError();
+        e = colsum<RED_L4>(nm, B, nullptr, dy, a3, nullptr, red, d_grad, 0, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_l4_bwd_dz, dim3(B, nm), dim3(256), 0, s, dy, wbf, z3, B, dz3);
+            e = hipGetLastError();
+        }
     }
     // layers 3 and 2: weight gradients dW = dz^T a_prev, bias gradients, and dz_prev
     const bf16_t *dzs[2] = {dz3, dz2};
@@ -486,8 +528,7 @@ extern "C" int bm_mlp_backward(uint32_t n_members, const float *d_params, const 
         g.out_f = d_grad + woff[l]; g.out_mstride = NPARAM; g.ldc = H;
         e = gemm<EPI_STORE, true, true>(g, (int)nm, s);
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL(k_bias_grad, dim3(1, nm), dim3(256), 0, s, dzs[l], B, d_grad, boff[l]);
-        e = hipGetLastError();
+        e = colsum<RED_BIAS>(nm, B, dzs[l], nullptr, nullptr, nullptr, red, d_grad, boff[l], s);
         if (e != hipSuccess) break;
         GemmArgs d = gemm_args();
         d.A = dzs[l]; d.a_mstride = (uint64_t)B * H; d.lda = H;          // (m = row, k = out)
@@ -498,8 +539,7 @@ extern "C" int bm_mlp_backward(uint32_t n_members, const float *d_params, const 
         e = gemm<EPI_DGRAD, false, true>(d, (int)nm, s);
     }
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_l1_bwd, dim3(1, nm), dim3(256), 0, s, dz1, u, B, d_grad);
-        e = hipGetLastError();
+        e = colsum<RED_L1>(nm, B, dz1, nullptr, nullptr, u, red, d_grad, 0, s);
     }
     return e == hipSuccess ? ok() : hip_fail(e, "bm_mlp_backward");
 }

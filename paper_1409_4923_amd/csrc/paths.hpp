@@ -12,7 +12,8 @@ namespace bm {
 
 enum : int { DYN_OVERDAMPED = 0, DYN_INERTIAL = 1 };
 enum : int { POT_SIN = 0, POT_RATCHET = 1, POT_TENT = 2, POT_FREE = 3 };
-enum : int { NZ_GAUSS = 1, NZ_POISSON = 2, NZ_DICH = 4 };
+enum : int { NZ_GAUSS = 1, NZ_POISSON = 2, NZ_DICH = 4,
+             NZ_NORMAL = 8 };   // Gaussian noise with normal increments (non-simplified scheme)
 
 template <typename R> struct Path {
     R x;           // folded position
@@ -63,6 +64,32 @@ template <int POT> __device__ __forceinline__ double force_plus(double x, double
     } else {
         return A;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Normal increments of the non-simplified scheme: the Box-Muller transform of
+// two uniform words, r = sqrt(-2 ln(1 - phi1)), (r cos 2 pi phi2, r sin 2 pi phi2)
+// with phi = w 2^-32.  1 - phi1 = (2^32 - w1) 2^-32 is formed from the integer,
+// so it is exact before the conversion and never 0.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void normal_pair(uint32_t w1, uint32_t w2, float &zc, float &zs)
+{
+    constexpr float NEG_2LN2 = -1.38629436111989061f;            // -2 ln 2
+    const float om = w1 ? (float)(0u - w1) * 0x1p-32f : 1.0f;
+    const float r = __builtin_amdgcn_sqrtf(NEG_2LN2 * __builtin_amdgcn_logf(om));   // log2, then scale
+    const float t = (float)w2 * 0x1p-32f;                        // turns: v_sin/v_cos take 2 pi t
+    zc = r * __builtin_amdgcn_cosf(t);
+    zs = r * __builtin_amdgcn_sinf(t);
+}
+
+__device__ __forceinline__ void normal_pair(uint32_t w1, uint32_t w2, double &zc, double &zs)
+{
+    constexpr double PI = 3.14159265358979323846;
+    const double om = w1 ? (double)(0u - w1) * 0x1p-32 : 1.0;
+    const double r = sqrt(-2.0 * log(om));
+    const double t = (double)w2 * 0x1p-32;
+    zc = r * cos(2.0 * PI * t);
+    zs = r * sin(2.0 * PI * t);
 }
 
 // Constant part of -V'(x) moved into the drive table.

@@ -116,8 +116,9 @@ template <typename R, int NOISE> constexpr uint32_t queue_bytes()
 // The integration loop: advances PPL paths per lane over steps [n0, n1) in
 // windows of JW steps (aligned to multiples of JW).  Per window the jumps are
 // queued, then the steps run in blocks of 16 sharing one Philox call for
-// Algorithm 2 (4 words x 4 base-6 digits) and 17 scalar loads of the forcing
-// table; x is folded after every step whose index is a multiple of 16.
+// Algorithm 2 (4 words x 4 base-6 digits; the normal increments of the
+// non-simplified scheme take one call per 4 steps) and 17 scalar loads of the
+// forcing table; x is folded after every step whose index is a multiple of 16.
 // smem holds the jump queues, slot-major with stride qs; column col(j) is this
 // lane's j-th path.
 // ---------------------------------------------------------------------------
@@ -173,6 +174,15 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                     for (uint32_t t = 0; t < (uint32_t)(n & 3u); ++t) u = times6(u);
                     dxi = three_point<R>(u, g3);
                 }
+                if constexpr ((NOISE & NZ_NORMAL) != 0) {
+                    // step n: words (2j, 2j+1) of block n/4, j = (n mod 4)/2; cos even, sin odd
+                    const U4 q = philox4x32_10((uint32_t)(n >> 2), path[j], a.point, TAG_GAUSS,
+                                               a.key0, a.key1);
+                    const bool hi = ((n >> 1) & 1u) != 0;
+                    R zc, zs;
+                    normal_pair(hi ? q.z : q.x, hi ? q.w : q.y, zc, zs);
+                    dxi = g3 * ((n & 1u) ? zs : zc);
+                }
                 full_step<R, DYN, POT, NOISE>(a, path[j], s[j], J[j], kq + col(j), fq + col(j), qs, off,
                                               dxi, h, hh, ngam, A0, A1, Fa, Fb);
             }
@@ -204,6 +214,16 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                 uint32_t u[PPL];
 #pragma unroll
                 for (int j = 0; j < PPL; ++j) u[j] = pick(q[j], (uint32_t)wd);
+                R zn[PPL][4];                         // normal increments of steps 4 wd .. 4 wd + 3
+                if constexpr ((NOISE & NZ_NORMAL) != 0) {
+#pragma unroll
+                    for (int j = 0; j < PPL; ++j) {
+                        const U4 qn = philox4x32_10((uint32_t)(n >> 2) + (uint32_t)wd, path[j], a.point,
+                                                    TAG_GAUSS, a.key0, a.key1);
+                        normal_pair(qn.x, qn.y, zn[j][0], zn[j][1]);
+                        normal_pair(qn.z, qn.w, zn[j][2], zn[j][3]);
+                    }
+                }
 #pragma unroll
                 for (int dg = 0; dg < 4; ++dg) {
                     const R A0 = A[4 * wd + dg], A1 = A[4 * wd + dg + 1];
@@ -214,6 +234,7 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                             dxi = three_point<R>(u[j], g3);
                             u[j] = times6(u[j]);   // next base-6 digit
                         }
+                        if constexpr ((NOISE & NZ_NORMAL) != 0) dxi = g3 * zn[j][dg];
                         full_step<R, DYN, POT, NOISE>(a, path[j], s[j], J[j], kq + col(j), fq + col(j), qs,
                                                       off, dxi, h, hh, ngam, A0, A1, Fa, Fb);
                     }

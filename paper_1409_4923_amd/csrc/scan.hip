@@ -130,6 +130,8 @@ int validate_scan(const bm_model *models, const bm_run *runs, size_t n)
     for (size_t i = 0; i < n; ++i) {
         int rc = validate(&models[i], &runs[i]);
         if (rc) return fail(rc, "point %zu: %s", i, last_error_text());
+        if (models[i].noise & BM_NOISE_NORMAL)
+            return fail(BM_ERR_UNSUPPORTED, "point %zu: the scan runs the three-point scheme only", i);
         if (runs[i].n_steps <= runs[i].window_start)
             return fail(BM_ERR_INVALID_ARG, "point %zu: n_steps must exceed window_start", i);
         if (runs[i].n_steps > 0xFFFFFFFFull) return fail(BM_ERR_UNSUPPORTED, "point %zu: n_steps >= 2^32", i);

@@ -74,10 +74,12 @@ def train(sur: "B.Surrogate", x: np.ndarray, y: np.ndarray, epochs: int, batch: 
     k = 0
     for ep in range(epochs):
         perm = np.stack([rng.permutation(boot[m]) for m in range(sur.n)])
+        # one upload per epoch, laid out [step][member][row] so each step's slice is contiguous
+        perm = perm[:, :steps_per_epoch * batch].reshape(sur.n, steps_per_epoch, batch).transpose(1, 0, 2)
+        perm_d = torch.tensor(np.ascontiguousarray(perm, dtype=np.int32), device=sur.device)
         losses = []
         for s in range(steps_per_epoch):
-            idx = torch.tensor(perm[:, s * batch:(s + 1) * batch].astype(np.int32), device=sur.device)
-            loss = sur.backward(xd, yd, idx)
+            loss = sur.backward(xd, yd, perm_d[s])
             frac = k / max(1, total - 1)
             sur.adam(lr * (lr_final / lr) ** frac)        # exponential decay to lr_final
             k += 1

@@ -116,7 +116,8 @@ def test_workspace_size_valid_configs():
     ("size", 0, B.BM_ERR_INVALID_ARG),
     ("dyn", 7, B.BM_ERR_INVALID_ARG),
     ("pot", 9, B.BM_ERR_INVALID_ARG),
-    ("noise", 8, B.BM_ERR_INVALID_ARG),
+    ("noise", 16, B.BM_ERR_INVALID_ARG),
+    ("noise", 9, B.BM_ERR_INVALID_ARG),            # three-point and normal increments together
     ("prec", 3, B.BM_ERR_INVALID_ARG),
     ("gamma", 0.0, B.BM_ERR_INVALID_ARG),
     ("gamma", float("nan"), B.BM_ERR_INVALID_ARG),
@@ -134,6 +135,13 @@ def test_invalid_arguments_rejected(field, value, code):
     rc, _ = _ws_rc(m, r)
     assert rc == code, (field, value, rc, B.last_error())
     assert B.last_error() != ""
+
+
+def test_normal_increments_accepted():
+    for noise in (W.NORMAL, W.NORMAL | W.POISSON, W.NORMAL | W.DICH, W.NORMAL | W.POISSON | W.DICH):
+        m, r = W.to_c(W.C3.with_(noise=noise, dyn=W.INERTIAL, gamma=0.9))
+        rc, _ = _ws_rc(m, r)
+        assert rc == B.BM_OK, (noise, B.last_error())
 
 
 def test_drive_needs_steps_per_period():
@@ -206,6 +214,8 @@ def test_scan_workspace_and_validation():
     assert B.lib().bm_scan_workspace_size(M, R, 0, ctypes.byref(n)) == B.BM_ERR_INVALID_ARG
     M2, R2 = _scan_arrays([pts[0], pts[1].with_(pot=W.POT_RATCHET)])
     assert B.lib().bm_scan_workspace_size(M2, R2, 2, ctypes.byref(n)) == B.BM_ERR_UNSUPPORTED
+    M4, R4 = _scan_arrays([pts[0].with_(noise=W.NORMAL)])
+    assert B.lib().bm_scan_workspace_size(M4, R4, 1, ctypes.byref(n)) == B.BM_ERR_UNSUPPORTED
     M3, R3 = _scan_arrays([pts[0].with_(n_window=pts[0].n_steps)])
     assert B.lib().bm_scan_workspace_size(M3, R3, 1, ctypes.byref(n)) == B.BM_ERR_INVALID_ARG
     assert "point 0" in B.last_error()

@@ -65,7 +65,8 @@ def _model_matrix():
     cases = []
     for dyn in (W.OVERDAMPED, W.INERTIAL):
         for pot in (W.POT_SIN, W.POT_RATCHET, W.POT_TENT, W.POT_FREE):
-            for noise in range(8):
+            for noise in list(range(8)) + [W.NORMAL, W.NORMAL | W.POISSON, W.NORMAL | W.DICH,
+                                            W.NORMAL | W.POISSON | W.DICH]:
                 cases.append((dyn, pot, noise))
     return cases
 
@@ -134,7 +135,9 @@ def test_fp64_per_path_jump_models(w):
 # ---------------------------------------------------------------------------
 # FP32 paths
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("w", [W.C1, W.C2, W.C3], ids=["c1-model", "c2-model", "c3-model"])
+@pytest.mark.parametrize("w", [W.C1, W.C2, W.C3, W.C1.with_(noise=W.NORMAL),
+                               W.C2.with_(noise=W.NORMAL | W.POISSON)],
+                         ids=["c1-model", "c2-model", "c3-model", "c1-normal", "c2-normal"])
 def test_fp32_noise_decisions_exact_and_states_close(w):
     w = w.with_(prec=W.F32, n_paths=2048)
     n = 300
@@ -156,7 +159,8 @@ def _ensemble_case(w, n_steps, n_window):
     _ensemble_case(W.C1.with_(prec=W.F32), 20000, 10000),
     _ensemble_case(W.C2, 40000, 20000),
     _ensemble_case(W.C3, 100000, 10000),
-], ids=["c1-f32", "c2-f32", "c3-f32"])
+    _ensemble_case(W.C1.with_(prec=W.F32, noise=W.NORMAL), 20000, 10000),
+], ids=["c1-f32", "c2-f32", "c3-f32", "c1-normal-f32"])
 def test_fp32_mean_velocity_within_3se(w):
     say("FP32 <v> vs FP64 oracle: %s, %d paths x %d steps" % (w.name, w.n_paths, w.n_steps))
     e, ps = gpu_run(w, [w.n_steps])
