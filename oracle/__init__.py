@@ -28,7 +28,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 OVERDAMPED, INERTIAL = 0, 1
 POT_SIN, POT_RATCHET, POT_TENT, POT_FREE, POT_HARMONIC = 0, 1, 2, 3, 4
-GAUSS, POISSON, DICH, NORMAL = 1, 2, 4, 8
+GAUSS, POISSON, DICH, NORMAL, JUMP_GRID = 1, 2, 4, 8, 16
 
 
 def build(force: bool = True) -> str:
@@ -58,7 +58,7 @@ class _Params(ctypes.Structure):
 
 
 PATH_DTYPE = np.dtype([("x", "<f8"), ("w", "<i8"), ("v", "<f8"), ("xi", "<f8"), ("wi", "<i8"),
-                       ("sP", "<i8"), ("kP", "<u8"), ("sD", "<i8"), ("mD", "<u8"),
+                       ("sP", "<i8"), ("thP", "<f8"), ("kP", "<u8"), ("sD", "<i8"), ("mD", "<u8"),
                        ("d", "<i4"), ("pad", "<i4")])
 
 _lib = None
@@ -101,7 +101,8 @@ class Params:
     pot: POT_SIN (V = sin 2 pi x), POT_RATCHET (V = -sin 2 pi x - sin(4 pi x)/4),
          POT_TENT (eq. 2, L = 2), POT_FREE, POT_HARMONIC (V = k x^2 / 2).
     noise: bit mask of GAUSS | POISSON | DICH (NORMAL: Gaussian noise with normal
-           increments instead of the three-point ones).
+           increments instead of the three-point ones; JUMP_GRID with POISSON: kicks
+           at their exact times, the step split around them).
     Poisson (eqs. 3-6): lam, zeta.  Dichotomous (eqs. 13-14): levels -Fa / +Fb,
     leaving rates mua (of -Fa) and mub (of +Fb).
     spp > 0: dt = (2 pi / omega) / spp unless dt is given; drive phase = n mod spp.

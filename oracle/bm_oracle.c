@@ -122,7 +122,8 @@ enum { OR_POT_SIN = 0,      /* V = sin(2 pi x), L = 1                    */
        OR_POT_FREE = 3,     /* V = 0 (test potential), L = 1             */
        OR_POT_HARMONIC = 4  /* V = k x^2/2 (test potential), no folding  */ };
 enum { OR_GAUSS = 1, OR_POISSON = 2, OR_DICH = 4,
-       OR_NORMAL = 8   /* Gaussian noise with normal increments (non-simplified scheme) */ };
+       OR_NORMAL = 8,      /* Gaussian noise with normal increments (non-simplified scheme) */
+       OR_JUMP_GRID = 16   /* Poisson kicks at their exact times (jump-adapted grid)        */ };
 
 typedef struct {
     int32_t dyn, pot, noise, literal_alg1;
@@ -148,6 +149,7 @@ typedef struct {
     double xi;      /* folded position at the window start             */
     int64_t wi;     /* folded periods at the window start              */
     int64_t sP;     /* Algorithm 3 countdown                           */
+    double thP;     /* jump-adapted grid: fraction of its step at which the next kick falls */
     uint64_t kP;    /* Poisson kicks drawn so far                      */
     int64_t sD;     /* Algorithm 4 countdown                           */
     uint64_t mD;    /* dichotomous flips so far                        */
@@ -244,12 +246,21 @@ static double drive(const or_params *P, int64_t j)
     return P->a * cos(2.0 * PI * (double)k / (double)P->spp) + P->F;
 }
 
-/* Drift of eq. (24) (overdamped) or of the inertial extension, evaluated at
- * step index j with the constant-within-step forcing `c` (R1). */
-static void drift(const or_params *P, double x, double v, int64_t j, double c,
+/* Periodic drive plus tilt at the time t_j + theta dt inside step j (0 < theta < 1),
+ * needed only on the jump-adapted grid. */
+static double drive_at(const or_params *P, int64_t j, double theta)
+{
+    if (P->spp <= 0) return P->F;
+    int64_t k = j % P->spp;
+    return P->a * cos(2.0 * PI * ((double)k + theta) / (double)P->spp) + P->F;
+}
+
+/* Drift of eq. (24) (overdamped) or of the inertial extension, with the drive
+ * value A and the constant-within-step forcing `c` (R1). */
+static void drift(const or_params *P, double x, double v, double A, double c,
                   double *fx, double *fv)
 {
-    double f = minus_dV(P, x) + drive(P, j) + c;
+    double f = minus_dV(P, x) + A + c;
     if (P->dyn == OR_INERTIAL) {
         *fx = v;
         *fv = -P->gamma * v + f;
@@ -284,8 +295,16 @@ void or_init(const or_params *P, uint64_t first_path, uint64_t count, or_path *o
              ? P->v0_lo + (P->v0_hi - P->v0_lo) * ((double)I[1] * 0x1p-32) : 0.0;
         s->w = 0;
         fold(P, s);
-        if (P->noise & OR_POISSON)
-            s->sP = (int64_t)floor(expo_from_word(I[2]) / (P->lambda * P->dt));
+        if (P->noise & OR_POISSON) {
+            if (P->noise & OR_JUMP_GRID) {
+                /* first kick time in steps: whole steps before its step, fraction within it */
+                double T = expo_from_word(I[2]) / (P->lambda * P->dt);
+                s->sP = (int64_t)floor(T);
+                s->thP = T - (double)s->sP;
+            } else {
+                s->sP = (int64_t)floor(expo_from_word(I[2]) / (P->lambda * P->dt));
+            }
+        }
         if (P->noise & OR_DICH) {
             /* stationary law: Pr{+Fb} = mu_a / (mu_a + mu_b) (rate into +Fb over total) */
             int dstar = ((double)I[3] * 0x1p-32 < P->mua / (P->mua + P->mub)) ? 1 : 0;
@@ -297,39 +316,90 @@ void or_init(const or_params *P, uint64_t first_path, uint64_t count, or_path *o
 }
 
 /* ------------------------------------------------------------------------ */
+/* Algorithm 1 over one interval of length h: predictor-corrector with the   */
+/* drive value A0 at its start and A1 at its end, constant forcing c, noise  */
+/* increment dxi and kick z (added once, in the corrector).  `lit` is the    */
+/* as-printed variant's extra forcing increment (R1).                         */
+/* ------------------------------------------------------------------------ */
+static void predictor_corrector(const or_params *P, double *px, double *pv, double h, double dxi,
+                                double z, double c, double lit, double A0, double A1)
+{
+    double x = *px, v = *pv;
+    double F1x, F1v, F2x, F2v;
+    double xb, vb;
+    drift(P, x, v, A0, c, &F1x, &F1v);
+    if (P->dyn == OR_INERTIAL) {
+        xb = x + F1x * h;
+        vb = v + F1v * h + dxi;
+        drift(P, xb, vb, A1, c, &F2x, &F2v);
+        xb = x + 0.5 * (F1x + F2x) * h;               /* predictor */
+        vb = v + 0.5 * (F1v + F2v) * h + dxi;
+        drift(P, xb, vb, A1, c, &F2x, &F2v);
+        double xn = x + 0.5 * (F1x + F2x) * h;        /* corrector */
+        double vn = v + 0.5 * (F1v + F2v) * h + dxi + z;
+        vn += lit * h;
+        *px = xn; *pv = vn;
+    } else {
+        xb = x + F1x * h + dxi;
+        drift(P, xb, v, A1, c, &F2x, &F2v);
+        xb = x + 0.5 * (F1x + F2x) * h + dxi;         /* predictor */
+        drift(P, xb, v, A1, c, &F2x, &F2v);
+        double xn = x + 0.5 * (F1x + F2x) * h + dxi + z; /* corrector */
+        xn += lit * h;
+        *px = xn;
+    }
+}
+
+/* Gaussian noise intensity factor G of the component receiving the noise. */
+static double noise_G(const or_params *P)
+{
+    return (P->dyn == OR_INERTIAL) ? sqrt(2.0 * P->gamma * P->D) : sqrt(2.0 * P->D);
+}
+
+/* Unit Gaussian increment of the interval that follows kick k on the
+ * jump-adapted grid (tag 5, indexed by kick number like tag 0 by step):
+ * three-point value in {-1, 0, +1} (to be scaled by G sqrt(3 h_sub)) or a
+ * standard normal (to be scaled by G sqrt(h_sub)). */
+static double kick_interval_noise(const or_params *P, uint64_t path, uint64_t k)
+{
+    uint32_t w[4];
+    if (P->noise & OR_GAUSS) {
+        draw(P, (uint32_t)(k / 16), path, 5u, w);
+        uint32_t u = w[(k % 16) / 4];
+        for (uint64_t j = 0; j < k % 4; ++j) u = (uint32_t)((uint64_t)u * 6u);
+        int digit = (int)(((uint64_t)u * 6u) >> 32);
+        return digit == 0 ? -1.0 : (digit == 1 ? 1.0 : 0.0);
+    }
+    if (P->noise & OR_NORMAL) {
+        draw(P, (uint32_t)(k / 4), path, 5u, w);
+        int j = (int)((k % 4) / 2);
+        double phi1 = (double)w[2 * j] * 0x1p-32;
+        double phi2 = (double)w[2 * j + 1] * 0x1p-32;
+        double r = sqrt(-2.0 * log(1.0 - phi1));
+        return (k % 2 == 0) ? r * cos(2.0 * PI * phi2) : r * sin(2.0 * PI * phi2);
+    }
+    return 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* One step n -> n+1 of one path.                                            */
 /* ------------------------------------------------------------------------ */
 static void step(const or_params *P, uint64_t path, int64_t n, or_path *s)
 {
     const double h = P->dt;
 
-    /* Algorithm 2: Gaussian increment, G = sqrt(2 D_G) (inertial: sqrt(2 gamma D)). */
-    double dxi = 0.0;
+    /* Algorithm 2: Gaussian increment, G = sqrt(2 D_G) (inertial: sqrt(2 gamma D)).
+     * unit = the draw before its scale (three-point value or standard normal). */
+    double dxi = 0.0, unit = 0.0;
     if (P->noise & OR_GAUSS) {
-        double G = (P->dyn == OR_INERTIAL) ? sqrt(2.0 * P->gamma * P->D) : sqrt(2.0 * P->D);
-        dxi = (double)or_three_point(P, path, n) * G * sqrt(3.0 * h);
+        unit = (double)or_three_point(P, path, n);
+        dxi = unit * noise_G(P) * sqrt(3.0 * h);
     } else if (P->noise & OR_NORMAL) {
-        double G = (P->dyn == OR_INERTIAL) ? sqrt(2.0 * P->gamma * P->D) : sqrt(2.0 * P->D);
-        dxi = or_normal(P, path, n) * G * sqrt(h);
+        unit = or_normal(P, path, n);
+        dxi = unit * noise_G(P) * sqrt(h);
     }
 
-    /* Algorithm 3: Poissonian increment (kick amplitude z; bias a = lambda zeta). */
-    double z = 0.0, bias = 0.0;
-    if (P->noise & OR_POISSON) {
-        bias = P->lambda * P->zeta;
-        if (s->sP <= 0) {
-            uint32_t J[4];
-            draw(P, (uint32_t)(s->kP / 2), path, 1u, J);
-            int half = (int)(s->kP % 2);
-            s->sP = (int64_t)floor(expo_from_word(J[2 * half]) / (P->lambda * h));
-            z = P->zeta * expo_from_word(J[2 * half + 1]);
-            s->kP += 1;
-        } else {
-            s->sP -= 1;
-        }
-    }
-
-    /* Algorithm 4: dichotomous increment. */
+    /* Algorithm 4: dichotomous increment (constant over the step). */
     double Gam = 0.0;
     if (P->noise & OR_DICH) {
         if (s->sD <= 0) {
@@ -345,31 +415,65 @@ static void step(const or_params *P, uint64_t path, int64_t n, or_path *s)
         Gam = s->d ? P->Fb : -P->Fa;
     }
 
-    /* Algorithm 1: predictor-corrector.  e = component receiving the noise. */
-    double c = P->literal_alg1 ? 0.0 : (Gam - bias);
-    double x = s->x, v = s->v;
-    double F1x, F1v, F2x, F2v;
-    double xb, vb;
-    drift(P, x, v, n, c, &F1x, &F1v);
-    if (P->dyn == OR_INERTIAL) {
-        xb = x + F1x * h;
-        vb = v + F1v * h + dxi;
-        drift(P, xb, vb, n + 1, c, &F2x, &F2v);
-        xb = x + 0.5 * (F1x + F2x) * h;               /* predictor */
-        vb = v + 0.5 * (F1v + F2v) * h + dxi;
-        drift(P, xb, vb, n + 1, c, &F2x, &F2v);
-        double xn = x + 0.5 * (F1x + F2x) * h;        /* corrector */
-        double vn = v + 0.5 * (F1v + F2v) * h + dxi + z;
-        if (P->literal_alg1) vn += (Gam - bias) * h;
-        s->x = xn; s->v = vn;
+    double bias = (P->noise & OR_POISSON) ? P->lambda * P->zeta : 0.0;
+
+    if ((P->noise & OR_POISSON) && (P->noise & OR_JUMP_GRID)) {
+        /* Jump-adapted grid: the kicks of this step fall at fractions theta of it;
+         * the step is split at each, every piece integrated by Algorithm 1 with
+         * its own length and Gaussian increment, the kick added at its end. */
+        double c = Gam - bias;
+        if (s->sP > 0) {
+            s->sP -= 1;
+            predictor_corrector(P, &s->x, &s->v, h, dxi, 0.0, c, 0.0, drive(P, n), drive(P, n + 1));
+        } else {
+            double from = 0.0, u = unit;
+            double A_from = drive(P, n);
+            for (;;) {
+                double th = s->thP;                  /* next kick inside this step */
+                double hs = (th - from) * h;
+                double scale = (P->noise & OR_GAUSS) ? noise_G(P) * sqrt(3.0 * hs)
+                                                     : noise_G(P) * sqrt(hs);
+                double A_th = drive_at(P, n, th);
+                uint32_t J[4];
+                draw(P, (uint32_t)(s->kP / 2), path, 1u, J);
+                int half = (int)(s->kP % 2);
+                double z = P->zeta * expo_from_word(J[2 * half + 1]);
+                predictor_corrector(P, &s->x, &s->v, hs, u * scale, z, c, 0.0, A_from, A_th);
+                /* next kick time, counted from this one */
+                double T = th + expo_from_word(J[2 * half]) / (P->lambda * h);
+                u = kick_interval_noise(P, path, s->kP);
+                s->kP += 1;
+                s->sP = (int64_t)floor(T);
+                s->thP = T - (double)s->sP;
+                from = th;
+                A_from = A_th;
+                if (s->sP > 0) break;
+            }
+            /* last piece, to the end of the step */
+            double hs = (1.0 - from) * h;
+            double scale = (P->noise & OR_GAUSS) ? noise_G(P) * sqrt(3.0 * hs) : noise_G(P) * sqrt(hs);
+            predictor_corrector(P, &s->x, &s->v, hs, u * scale, 0.0, c, 0.0, A_from, drive(P, n + 1));
+            s->sP -= 1;
+        }
     } else {
-        xb = x + F1x * h + dxi;
-        drift(P, xb, v, n + 1, c, &F2x, &F2v);
-        xb = x + 0.5 * (F1x + F2x) * h + dxi;         /* predictor */
-        drift(P, xb, v, n + 1, c, &F2x, &F2v);
-        double xn = x + 0.5 * (F1x + F2x) * h + dxi + z; /* corrector */
-        if (P->literal_alg1) xn += (Gam - bias) * h;
-        s->x = xn;
+        /* Algorithm 3: Poissonian increment on the fixed grid (R3). */
+        double z = 0.0;
+        if (P->noise & OR_POISSON) {
+            if (s->sP <= 0) {
+                uint32_t J[4];
+                draw(P, (uint32_t)(s->kP / 2), path, 1u, J);
+                int half = (int)(s->kP % 2);
+                s->sP = (int64_t)floor(expo_from_word(J[2 * half]) / (P->lambda * h));
+                z = P->zeta * expo_from_word(J[2 * half + 1]);
+                s->kP += 1;
+            } else {
+                s->sP -= 1;
+            }
+        }
+        /* Algorithm 1: predictor-corrector. */
+        double c = P->literal_alg1 ? 0.0 : (Gam - bias);
+        double lit = P->literal_alg1 ? (Gam - bias) : 0.0;
+        predictor_corrector(P, &s->x, &s->v, h, dxi, z, c, lit, drive(P, n), drive(P, n + 1));
     }
 
     fold(P, s);                                     /* x mod L (Sec. 4) */

@@ -563,3 +563,113 @@ def test_free_diffusion_normal_increments(orc):
     dx = orc.unwrapped(P, st) - x0
     # a sum of normals is normal with variance 2 D t
     assert sps.kstest(dx / math.sqrt(2 * P.D * n * P.dt), "norm").pvalue > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Jump-adapted grid: Poisson kicks at their exact times (the step is split)
+# ---------------------------------------------------------------------------
+def _kick_times(orc, P, path, t_end):
+    """Kick times and amplitudes of one path written out from the Philox words
+    (first waiting time: word 2 of the tag-2 block; kick k: tag-1 block k/2,
+    words 2(k mod 2) (next waiting time) and 2(k mod 2)+1 (amplitude))."""
+    key = (P.seed & 0xFFFFFFFF, P.seed >> 32)
+    E = lambda w: -math.log(1.0 - w * 2.0 ** -32)
+    t = E(orc.philox4x32_10((0, path, P.point, 2), key)[2]) / P.lam
+    out = []
+    k = 0
+    while t < t_end:
+        J = orc.philox4x32_10((k // 2, path, P.point, 1), key)
+        half = k % 2
+        out.append((t, P.zeta * E(J[2 * half + 1])))
+        t += E(J[2 * half]) / P.lam
+        k += 1
+    return out
+
+
+def test_jump_grid_kicks_at_exact_times(orc):
+    """V = 0, no Gaussian noise: x(T) - x0 = sum of the kicks up to T - lambda zeta T,
+    whatever the step, path by path."""
+    for dt in (0.1, 0.013):
+        P = orc.Params(pot=orc.POT_FREE, noise=orc.POISSON | orc.JUMP_GRID, lam=3.0, zeta=0.2, dt=dt,
+                       seed=77, x0_lo=0.0, x0_hi=1.0)
+        n = int(round(4.0 / dt))
+        T = n * dt
+        st0 = orc.init(P, 0, 40)
+        st = orc.advance(P, st0.copy(), 0, 0, n)
+        dx = orc.unwrapped(P, st) - orc.unwrapped(P, st0)
+        for p in range(40):
+            kicks = _kick_times(orc, P, p, T)
+            want = sum(z for _, z in kicks) - P.lam * P.zeta * T
+            assert abs(dx[p] - want) < 1e-10
+            assert st["kP"][p] == len(kicks)
+
+
+def test_jump_grid_kick_counts_unbiased_at_coarse_step(orc):
+    """lambda dt = 0.5: on the fixed grid the kick rate is (1 - e^{-lambda dt})/dt
+    (21% low); on the jump-adapted grid the count over [0, T] is Poisson(lambda T)."""
+    lam, dt, n, N = 5.0, 0.1, 100, 20000
+    T = n * dt
+    for mode, rate in ((orc.POISSON | orc.JUMP_GRID, lam), (orc.POISSON, -math.expm1(-lam * dt) / dt)):
+        P = orc.Params(pot=orc.POT_FREE, noise=mode, lam=lam, zeta=0.1, dt=dt, seed=5)
+        st = orc.run(P, 0, N, n, threads=THREADS)
+        k = st["kP"].astype(np.float64)
+        if mode & orc.JUMP_GRID:
+            # kicks drawn = kicks at times < T (the next one is pending)
+            assert abs(k.mean() - lam * T) < 4 * math.sqrt(lam * T / N)
+            assert abs(k.var() / (lam * T) - 1.0) < 0.05
+        else:
+            assert abs(k.mean() - rate * T) < 4 * math.sqrt(lam * T / N) + 1.0
+            assert k.mean() < 0.85 * lam * T
+
+
+def _ou_kicked_exact(orc, P, p, x0, T):
+    """dx = -k x dt + dN_z - lambda zeta dt, solved exactly between and across kicks."""
+    k = P.k_harm
+    x = x0 * math.exp(-k * T) - P.lam * P.zeta * (1.0 - math.exp(-k * T)) / k
+    for t, z in _kick_times(orc, P, p, T):
+        x += z * math.exp(-k * (T - t))
+    return x
+
+
+def test_jump_grid_second_order_with_kicks(orc):
+    """Linear drift with kicks and no Gaussian noise: on the jump-adapted grid the
+    global error against the exact solution falls 4x when dt halves; on the fixed
+    grid the kicks are moved by up to dt and the error is first order."""
+    errs = {}
+    for mode in (orc.POISSON | orc.JUMP_GRID, orc.POISSON):
+        errs[mode] = []
+        for dt in (0.02, 0.01, 0.005):
+            P = orc.Params(pot=orc.POT_HARMONIC, k_harm=1.3, noise=mode, lam=2.0, zeta=0.5, dt=dt, seed=9,
+                           x0_lo=-1.0, x0_hi=1.0)
+            n = int(round(3.0 / dt))
+            st0 = orc.init(P, 0, 32)
+            st = orc.advance(P, st0.copy(), 0, 0, n)
+            e = [abs(st["x"][p] - _ou_kicked_exact(orc, P, p, st0["x"][p], n * dt)) for p in range(32)]
+            errs[mode].append(max(e))
+    adapted, fixed = errs[orc.POISSON | orc.JUMP_GRID], errs[orc.POISSON]
+    assert adapted[0] / adapted[1] > 3.3 and adapted[1] / adapted[2] > 3.3
+    assert fixed[1] / fixed[2] < 2.5 and fixed[2] > 10 * adapted[2]
+
+
+def test_jump_grid_gaussian_pieces_variance(orc):
+    """V = 0 with Gaussian noise: every piece of a split step gets its own increment of
+    variance G^2 h_piece, so the noise part of x(T) has variance 2 D T exactly."""
+    for g in (orc.GAUSS, orc.NORMAL):
+        P = orc.Params(pot=orc.POT_FREE, noise=g | orc.POISSON | orc.JUMP_GRID, lam=4.0, zeta=0.0, D=0.3,
+                       dt=0.05, seed=13)
+        n, N = 60, 20000
+        st0 = orc.init(P, 0, N)
+        st = orc.advance(P, st0.copy(), 0, 0, n, threads=THREADS)
+        dx = orc.unwrapped(P, st) - orc.unwrapped(P, st0)
+        var = 2 * P.D * n * P.dt
+        assert abs(dx.mean()) < 4 * math.sqrt(var / N)
+        assert abs(dx.var() / var - 1.0) < 4 * math.sqrt(2.0 / N) + 0.01
+
+
+def test_jump_grid_chunked_equals_whole(orc):
+    P = _c2_like(orc, noise=orc.GAUSS | orc.POISSON | orc.JUMP_GRID, lam=40.0)
+    a = orc.run(P, 100, 64, 1000)
+    b = orc.init(P, 100, 64)
+    orc.advance(P, b, 100, 0, 377)
+    orc.advance(P, b, 100, 377, 1000)
+    assert a.tobytes() == b.tobytes()
