@@ -237,7 +237,9 @@ def surrogate_leg(args):
     held-out points the ensemble routes (they are the costly, multi-attractor ones).
     A point counts as delivered at tolerance if MC computed it or if the ensemble
     answered it within 0.01 of the truth (measured on the held-out points).  The
-    amortised figure also charges label generation and training to the 10^6 queries."""
+    amortised figure also charges label generation and training to the 10^6 queries.
+    A second baseline gives plain MC (and the fallback) one path count for all points,
+    the largest any held-out point needs, as MC must without knowing sigma_i."""
     import numpy as np
     import torch
     from paper_1409_4923_amd import bmotor as B
@@ -286,6 +288,10 @@ def surrogate_leg(args):
     sur_rate = delivered / t_sur
     sur_rate_amortised = delivered / (t_sur + lab.seconds + t_train)
     mc_rate = 1.0 / mc_cost
+    # Plain MC that does not know sigma_i in advance: one path count for every point,
+    # the largest the held-out points need; the fallback then pays the same.
+    fixed_cost = float(np.max(need)) * n_steps / rate
+    sur_rate_fixed = delivered / (t_query + f * n_q * fixed_cost)
     flops = n_q * 5 * 2 * (5 * 256 + 2 * 256 * 256 + 256)
     return {"labels": args.labels, "label_budget": [args.label_paths, args.label_periods],
             "label_seconds": lab.seconds, "train_seconds": t_train, "epochs": args.epochs,
@@ -299,6 +305,8 @@ def surrogate_leg(args):
             "mc_seconds_per_point": mc_cost, "fallback_mc_seconds_per_point": fb_cost,
             "mc_points_per_s_at_tol": mc_rate, "surrogate_points_per_s_at_tol": sur_rate,
             "gain": sur_rate / mc_rate, "gain_amortised": sur_rate_amortised / mc_rate,
+            "fixed_n_paths": float(np.max(need)), "mc_points_per_s_fixed_n": 1.0 / fixed_cost,
+            "gain_vs_fixed_n": sur_rate_fixed * fixed_cost,
             "mlp_inference": {"achieved": flops / t_query / 1e12, "peak": 2500.0, "unit": "TFLOP/s (BF16 MFMA)",
                               "frac": flops / t_query / 2.5e15}}
 
@@ -318,7 +326,7 @@ def main():
     ap.add_argument("--labels", type=int, default=200_000)
     ap.add_argument("--label-paths", type=int, default=256)
     ap.add_argument("--label-periods", type=int, default=100)
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--heldout", type=int, default=10_000)
     ap.add_argument("--truth-paths", type=int, default=4096)
     ap.add_argument("--queries", type=int, default=1_000_000)
