@@ -77,6 +77,14 @@ extern "C" {
  * Philox block (n/4, path, point, tag 0): cos for even n, sin for odd n.  Excludes
  * BM_NOISE_GAUSS; ensembles only (bm_scan rejects it with BM_ERR_UNSUPPORTED). */
 #define BM_NOISE_NORMAL  8u
+/* With BM_NOISE_POISSON: the jump-adapted grid of Sec. 3 (kicks at their exact
+ * times t_i; waiting times E/lambda are not rounded to the step).  A step that holds
+ * kicks is cut at each t_i; each piece is integrated by Algorithm 1 with its own
+ * length and a Gaussian increment of matching variance (the step's own draw scaled
+ * by sqrt(piece/dt) for the first piece; for the piece after kick k a draw from tag
+ * 5 indexed by k), and the kick is added at the end of its piece.  Requires
+ * BM_NOISE_POISSON and shot_rate*dt <= 16; ensembles only (bm_scan rejects it). */
+#define BM_NOISE_JUMP_GRID 16u
 
 /* bm_run.prec: arithmetic of the path state (statistics are always FP64) */
 #define BM_F64 0u

@@ -24,7 +24,7 @@ BM_ERR_STATE = -5
 
 BM_OVERDAMPED, BM_INERTIAL = 0, 1
 BM_POT_SIN, BM_POT_RATCHET, BM_POT_TENT, BM_POT_FREE = 0, 1, 2, 3
-BM_NOISE_GAUSS, BM_NOISE_POISSON, BM_NOISE_DICH, BM_NOISE_NORMAL = 1, 2, 4, 8
+BM_NOISE_GAUSS, BM_NOISE_POISSON, BM_NOISE_DICH, BM_NOISE_NORMAL, BM_NOISE_JUMP_GRID = 1, 2, 4, 8, 16
 BM_F64, BM_F32 = 0, 1
 
 

@@ -67,7 +67,9 @@ int validate(const bm_model *m, const bm_run *r)
     if (r->size != sizeof(bm_run)) return fail(BM_ERR_INVALID_ARG, "bm_run.size mismatch");
     if (m->dyn > BM_INERTIAL) return fail(BM_ERR_INVALID_ARG, "unknown dynamics %u", m->dyn);
     if (m->pot > BM_POT_FREE) return fail(BM_ERR_INVALID_ARG, "unknown potential %u", m->pot);
-    if (m->noise & ~15u) return fail(BM_ERR_INVALID_ARG, "unknown noise bits 0x%x", m->noise);
+    if (m->noise & ~31u) return fail(BM_ERR_INVALID_ARG, "unknown noise bits 0x%x", m->noise);
+    if ((m->noise & BM_NOISE_JUMP_GRID) && !(m->noise & BM_NOISE_POISSON))
+        return fail(BM_ERR_INVALID_ARG, "BM_NOISE_JUMP_GRID needs BM_NOISE_POISSON");
     if ((m->noise & BM_NOISE_GAUSS) && (m->noise & BM_NOISE_NORMAL))
         return fail(BM_ERR_INVALID_ARG, "BM_NOISE_GAUSS and BM_NOISE_NORMAL are alternatives");
     if (r->prec > BM_F32) return fail(BM_ERR_INVALID_ARG, "unknown precision %u", r->prec);
@@ -95,6 +97,8 @@ int validate(const bm_model *m, const bm_run *r)
             return fail(BM_ERR_INVALID_ARG, "shot_mean must be finite and >= 0");
         if (E_MAX / (m->shot_rate * dt) >= 2147483000.0)
             return fail(BM_ERR_UNSUPPORTED, "shot_rate*dt too small: waiting times overflow int32");
+        if ((m->noise & BM_NOISE_JUMP_GRID) && m->shot_rate * dt > 16.0)
+            return fail(BM_ERR_UNSUPPORTED, "jump-adapted grid needs shot_rate*dt <= 16");
     }
     if (m->noise & BM_NOISE_DICH) {
         if (!(fin(m->dich_Fa) && fin(m->dich_Fb) && m->dich_Fa >= 0 && m->dich_Fb >= 0))
@@ -127,7 +131,7 @@ size_t table_entries(const bm_run *r) { return (r->steps_per_period ? r->steps_p
 // Workspace layout (structure of arrays, each 256-byte aligned)
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t x, w, v, xi, wi, sP, kP, sD, mD, d, vp, part, tab, total;
+    size_t x, w, v, xi, wi, sP, kP, thP, sD, mD, d, vp, part, tab, total;
 };
 
 static size_t up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -146,6 +150,7 @@ static Layout layout(const bm_model *m, const bm_run *r)
     L.wi = take(N * 4);
     L.sP = take(N * 4);
     L.kP = take(N * 4);
+    L.thP = (m->noise & BM_NOISE_JUMP_GRID) ? take(N * 8) : 0;
     L.sD = take(N * 4);
     L.mD = take(N * 4);
     L.d = take(N * 4);
@@ -153,7 +158,6 @@ static Layout layout(const bm_model *m, const bm_run *r)
     L.part = take(((N + 63) / 64) * sizeof(Partial));
     L.tab = take(table_entries(r) * rs);
     L.total = o;
-    (void)m;
     return L;
 }
 
@@ -282,6 +286,8 @@ PointConst point_const(const bm_model *m, const bm_run *r, const void *d_tab)
         k.tol0_mua = (float)(2e-6 / k.mua_dt + 1e-6);
         k.tol0_mub = (float)(2e-6 / k.mub_dt + 1e-6);
     }
+    k.drive_a = r->steps_per_period ? m->drive_amp : 0.0;
+    k.drive_c = forcing_constant(m);
     k.x0_lo = r->x0_lo; k.x0_w = r->x0_hi - r->x0_lo;
     k.v0_lo = r->v0_lo; k.v0_w = r->v0_hi - r->v0_lo;
     return k;
@@ -299,6 +305,7 @@ static void fill_kargs(bm_ensemble *e)
     k.x = b + L.x; k.w = (int32_t *)(b + L.w); k.v = b + L.v; k.xi = b + L.xi;
     k.wi = (int32_t *)(b + L.wi);
     k.sP = (int32_t *)(b + L.sP); k.kP = (uint32_t *)(b + L.kP);
+    k.thP = (e->model.noise & BM_NOISE_JUMP_GRID) ? (double *)(b + L.thP) : nullptr;
     k.sD = (int32_t *)(b + L.sD); k.mD = (uint32_t *)(b + L.mD); k.d = (int32_t *)(b + L.d);
     k.vp = (double *)(b + L.vp);
     k.part = (Partial *)(b + L.part);

@@ -20,6 +20,9 @@ enum : uint32_t {
     TAG_POISSON = 1u,  // index = kick / 2; words (2 (kick % 2), 2 (kick % 2) + 1)
     TAG_INIT = 2u,     // index = 0; words: x0, v0, Poisson countdown, dichotomous state
     TAG_DICH = 3u,     // index = flip / 4; word flip % 4
+    TAG_KICK_NOISE = 5u, // jump-adapted grid: Gaussian increment of the piece after kick k
+                         // (three-point: index k / 16, word (k % 16) / 4, digit k % 4;
+                         //  normal: index k / 4, words (2j, 2j+1), j = (k % 4) / 2)
 };
 
 // Thresholds of Algorithm 2 on a 32-bit word u (fraction u / 2^32):
@@ -110,6 +113,8 @@ struct PointConst {
     double mua_dt, mub_dt;
     double p_hi;          // stationary Pr{+Fb} = mu_a / (mu_a + mu_b)
     double x0_lo, x0_w, v0_lo, v0_w;
+    double drive_a;       // drive amplitude (forcing inside a step on the jump-adapted grid)
+    double drive_c;       // constant forcing: tilt - Poisson bias + potential offset
     // FP32 estimates of the countdown X = E / (rate dt): X ~= -log2(1 - phi) * c,
     // trusted when its fraction is farther than tol0 + tol1 X from an integer.
     float c_lam, c_mua, c_mub;   // ln 2 / (rate dt)
@@ -133,6 +138,7 @@ struct KArgs {
     uint32_t *mD;         // dichotomous flips so far
     int32_t *d;           // dichotomous state (0: -Fa, 1: +Fb)
     double *vp;           // per-path velocity, eq. (31)
+    double *thP;          // jump-adapted grid: fraction of its step at which the next kick falls
     Partial *part;        // per-chunk partials
     PointConst p;
     uint64_t n0, n1;      // step range of this launch (export: first path, count)

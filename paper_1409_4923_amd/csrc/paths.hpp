@@ -13,7 +13,14 @@ namespace bm {
 enum : int { DYN_OVERDAMPED = 0, DYN_INERTIAL = 1 };
 enum : int { POT_SIN = 0, POT_RATCHET = 1, POT_TENT = 2, POT_FREE = 3 };
 enum : int { NZ_GAUSS = 1, NZ_POISSON = 2, NZ_DICH = 4,
-             NZ_NORMAL = 8 };   // Gaussian noise with normal increments (non-simplified scheme)
+             NZ_NORMAL = 8,     // Gaussian noise with normal increments (non-simplified scheme)
+             NZ_JGRID = 16 };   // Poisson kicks at their exact times (jump-adapted grid)
+
+// Poisson kicks pre-drawn per window into the LDS queue (fixed grid only).
+template <int NOISE> constexpr bool queued_kicks()
+{
+    return (NOISE & NZ_POISSON) != 0 && (NOISE & NZ_JGRID) == 0;
+}
 
 template <typename R> struct Path {
     R x;           // folded position
@@ -24,6 +31,7 @@ template <typename R> struct Path {
     int32_t sD;    // dichotomous countdown
     uint32_t mD;   // dichotomous flips so far
     int32_t d;     // dichotomous state
+    double thP;    // jump-adapted grid: fraction of its step at which the next kick falls
 };
 
 // ---------------------------------------------------------------------------
@@ -127,6 +135,16 @@ template <int POT, typename R> __device__ __forceinline__ void fold(Path<R> &s)
 constexpr uint32_t JW = 128;          // jump window, a multiple of 16 steps
 constexpr uint32_t JCAP = 8;          // queued jumps per lane and window
 constexpr uint32_t INLINE_BIT = 0x80000000u;
+
+// A kick of the jump-adapted grid, drawn ahead: its step offset in the window, the
+// fraction of that step at which it falls, its amplitude, and the Gaussian
+// increment (times G sqrt(3 dt) or G sqrt(dt)) of the piece that follows it.
+template <typename R> struct JGKick {
+    uint32_t off;
+    R th, z, u;
+};
+constexpr uint32_t JG_NONE = 0xFFFFFFFFu;
+constexpr uint32_t JG_CAP = 6;     // queued kicks per lane and window (Poisson(2) exceeds 6 w.p. 0.5%)
 
 template <typename R> struct KickEntry {
     uint32_t off;   // step offset in the window (>= window length: none left)

@@ -11,6 +11,12 @@ namespace bm {
 
 template <typename R> __device__ __forceinline__ R *arr(void *p) { return reinterpret_cast<R *>(p); }
 
+template <typename R>
+__device__ __forceinline__ R three_point(uint32_t u, R g3)
+{
+    return u < T_MINUS ? -g3 : (u < T_PLUS ? g3 : R(0));
+}
+
 template <typename R, int POT, int NOISE>
 __device__ __forceinline__ void load_path(const KArgs &a, uint32_t p, Path<R> &s)
 {
@@ -19,6 +25,8 @@ __device__ __forceinline__ void load_path(const KArgs &a, uint32_t p, Path<R> &s
     s.v = arr<R>(a.v)[p];
     if constexpr ((NOISE & NZ_POISSON) != 0) { s.sP = a.sP[p]; s.kP = a.kP[p]; }
     else { s.sP = 0; s.kP = 0u; }
+    if constexpr ((NOISE & NZ_JGRID) != 0) s.thP = a.thP[p];
+    else s.thP = 0.0;
     if constexpr ((NOISE & NZ_DICH) != 0) { s.sD = a.sD[p]; s.mD = a.mD[p]; s.d = a.d[p]; }
     else { s.sD = 0; s.mD = 0u; s.d = 0; }
 }
@@ -30,6 +38,7 @@ __device__ __forceinline__ void store_path(const KArgs &a, uint32_t p, const Pat
     a.w[p] = s.w;
     arr<R>(a.v)[p] = s.v;
     if constexpr ((NOISE & NZ_POISSON) != 0) { a.sP[p] = s.sP; a.kP[p] = s.kP; }
+    if constexpr ((NOISE & NZ_JGRID) != 0) a.thP[p] = s.thP;
     if constexpr ((NOISE & NZ_DICH) != 0) { a.sD[p] = s.sD; a.mD[p] = s.mD; a.d[p] = s.d; }
     if (a.snapshot) { arr<R>(a.xi)[p] = s.x; a.wi[p] = s.w; }
 }
@@ -43,24 +52,176 @@ template <typename R> __device__ __forceinline__ R drive_at(const PointConst &a,
 }
 
 // Per-lane cursor into the LDS jump queues of the current window.
+
 template <typename R> struct JumpCursor {
     uint32_t nP;    // offset of the next kick in the window
     R zP;           // its amplitude (< 0: kicks are drawn inline from nP on)
     uint32_t cP;    // element index of the next queue slot (slot * qs)
     uint32_t nD;    // offset of the next flip
     uint32_t cD;    // element index of the next queue slot (FLIP_INLINE: drawn inline)
+    // jump-adapted grid
+    JGKick<R> g;    // next kick (g.off == JG_NONE: none left in the window)
+    uint32_t gs;    // queue slot of g
+    uint32_t gn;    // kicks queued for this window
+    uint32_t poff;  // offset of the first kick not yet drawn
+    double pth;     // its fraction of the step (FP64: kick times decide the integer state)
 };
 constexpr uint32_t FLIP_INLINE = 0xFFFFFFFFu;
 
-// One step of one path at window offset `off`: jumps due at this step, then
-// Algorithm 1.  `dxi` is the Algorithm 2 increment.  (Folding is done by the caller.)
+// Forcing at the time t_n + theta dt inside a step of drive phase k (jump-adapted
+// grid): a cos(2 pi (k + theta) / spp) + tilt - Poisson bias + potential offset.
+// The phase k may be passed unreduced (k < spp + 16): cos is periodic in it.
+template <typename R> __device__ __forceinline__ R drive_inside(const PointConst &a, uint32_t k, double th)
+{
+    if constexpr (sizeof(R) == 4) {
+        const float turns = ((float)k + (float)th) / (float)a.spp;
+        return (float)a.drive_a * __builtin_amdgcn_cosf(turns) + (float)a.drive_c;
+    } else {
+        constexpr double PI = 3.14159265358979323846;
+        return a.drive_a * cos(2.0 * PI * ((double)k + th) / (double)a.spp) + a.drive_c;
+    }
+}
+
+// Gaussian increment (times G sqrt(3 dt) or G sqrt(dt)) of the piece that follows
+// kick k on the jump-adapted grid (tag 5, indexed by kick number).
+template <typename R, int NOISE>
+__device__ __forceinline__ R piece_noise(const PointConst &a, uint32_t path, uint32_t k, R g3)
+{
+    if constexpr ((NOISE & NZ_GAUSS) != 0) {
+        const U4 q = philox4x32_10(k >> 4, path, a.point, TAG_KICK_NOISE, a.key0, a.key1);
+        uint32_t u = pick(q, (k >> 2) & 3u);
+        for (uint32_t t = 0; t < (k & 3u); ++t) u = times6(u);
+        return three_point<R>(u, g3);
+    } else if constexpr ((NOISE & NZ_NORMAL) != 0) {
+        const U4 q = philox4x32_10(k >> 2, path, a.point, TAG_KICK_NOISE, a.key0, a.key1);
+        const bool hi = ((k >> 1) & 1u) != 0;
+        R zc, zs;
+        normal_pair(hi ? q.z : q.x, hi ? q.w : q.y, zc, zs);
+        return g3 * ((k & 1u) ? zs : zc);
+    } else {
+        return R(0);
+    }
+}
+
+// sqrt of a piece's fraction of the step: the hardware square root (1 ulp) in FP32,
+// the correctly rounded one in FP64.
+__device__ __forceinline__ float piece_sqrt(float f) { return __builtin_amdgcn_sqrtf(f); }
+__device__ __forceinline__ double piece_sqrt(double f) { return sqrt(f); }
+
+// Most kicks one step of the jump-adapted grid may hold (a Poisson(16) count
+// exceeds it with probability below 10^-1000).
+constexpr uint32_t JG_MAX_KICKS = 4096;
+
+// Draws the kick that falls at (off, th) of the window -- its amplitude, the
+// increment of the piece after it -- and the time of the next kick, counted from
+// it in FP64: off += floor(T), th = T - floor(T) with T = th + E / (lambda dt).
+template <typename R, int NOISE>
+__device__ __forceinline__ JGKick<R> jg_draw(const PointConst &a, uint32_t path, uint32_t &kP, uint32_t &off,
+                                             double &th)
+{
+    const U4 b = philox4x32_10(kP >> 1, path, a.point, TAG_POISSON, a.key0, a.key1);
+    const bool second = (kP & 1u) != 0u;
+    JGKick<R> e;
+    e.off = off;
+    e.th = (R)th;
+    e.z = amplitude<R>(a, second ? b.w : b.y);
+    e.u = piece_noise<R, NOISE>(a, path, kP, (R)a.g3);
+    const double T = th + expo64(second ? b.z : b.x) / a.lam_dt;
+    const double Tf = floor(T);
+    off += (uint32_t)Tf;                     // < 2^31 + window: validated on the host
+    th = T - Tf;
+    ++kP;
+    return e;
+}
+
+// Queue up to JG_CAP kicks of one window (wave-uniform loop, as for the fixed grid);
+// kicks beyond a full queue are drawn at their steps.
+template <typename R, int NOISE>
+__device__ __forceinline__ void jg_window(const PointConst &a, uint32_t path, uint32_t wlen, uint32_t &kP,
+                                          JumpCursor<R> &J, JGKick<R> *q, uint32_t qs)
+{
+    uint32_t slot = 0;
+    bool active = J.poff < wlen;
+    while (__any(active)) {
+        if (active) {
+            if (slot < JG_CAP) {
+                q[slot * qs] = jg_draw<R, NOISE>(a, path, kP, J.poff, J.pth);
+                ++slot;
+                active = J.poff < wlen;
+            } else {
+                active = false;
+            }
+        }
+    }
+    J.gn = slot;
+    J.gs = 0;
+    if (slot > 0) J.g = q[0];
+    else J.g.off = JG_NONE;
+}
+
+// Moves the cursor past the kick just applied.
+template <typename R, int NOISE>
+__device__ __forceinline__ void jg_advance(const PointConst &a, uint32_t path, uint32_t wlen, uint32_t &kP,
+                                           JumpCursor<R> &J, const JGKick<R> *q, uint32_t qs)
+{
+    ++J.gs;
+    if (J.gs < J.gn) J.g = q[J.gs * qs];
+    else if (J.poff < wlen) J.g = jg_draw<R, NOISE>(a, path, kP, J.poff, J.pth);    // queue overflow
+    else J.g.off = JG_NONE;
+}
+
+// One step of the jump-adapted grid.  Every lane integrates the first piece of its
+// step -- the whole step, or up to its first kick at t_n + theta dt -- with the
+// same instructions; lanes with a kick then integrate the remaining pieces (one
+// per further kick in the step, then the rest of the step).  The first piece
+// takes the step's own Gaussian increment scaled by sqrt(theta); a piece after
+// kick k takes the increment drawn for k.
+template <typename R, int DYN, int POT, int NOISE>
+__device__ __forceinline__ void jg_step(const PointConst &a, uint32_t path, Path<R> &s, JumpCursor<R> &J,
+                                        const JGKick<R> *q, uint32_t qs, uint32_t wlen, uint32_t off,
+                                        uint32_t kph, R dxi, R h, R hh, R ngam, R A0, R A1, R lev)
+{
+    const bool kick = J.g.off == off;
+    R th1 = R(1), A_e = A1, dxi1 = dxi, z1 = R(0);
+    if (kick) {
+        th1 = J.g.th;
+        A_e = drive_inside<R>(a, kph, (double)th1) + lev;
+        dxi1 = dxi * piece_sqrt(th1);
+        z1 = J.g.z;
+    }
+    pc_step<DYN, POT, true, R>(s, th1 * h, th1 * hh, ngam, dxi1, z1, A0, A_e);
+    if (kick) {
+        R from = th1, A_from = A_e, u = J.g.u;
+        jg_advance<R, NOISE>(a, path, wlen, s.kP, J, q, qs);
+        // further kicks in this step (lambda dt <= 16 is enforced on the host; the
+        // bound only guarantees that every lane leaves the loop)
+        for (uint32_t it = 0; J.g.off == off && it < JG_MAX_KICKS; ++it) {
+            const R th = J.g.th;
+            const R A_th = drive_inside<R>(a, kph, (double)th) + lev;
+            pc_step<DYN, POT, true, R>(s, (th - from) * h, (th - from) * hh, ngam, u * piece_sqrt(th - from), J.g.z,
+                                       A_from, A_th);
+            from = th;
+            A_from = A_th;
+            u = J.g.u;
+            jg_advance<R, NOISE>(a, path, wlen, s.kP, J, q, qs);
+        }
+        pc_step<DYN, POT, false, R>(s, (R(1) - from) * h, (R(1) - from) * hh, ngam, u * piece_sqrt(R(1) - from),
+                                    R(0), A_from, A1);
+    }
+}
+
+// One step of one path at window offset `off` (drive phase kph): jumps due at this
+// step, then Algorithm 1.  `dxi` is the Algorithm 2 increment.  (Folding is done
+// by the caller.)
 template <typename R, int DYN, int POT, int NOISE>
 __device__ __forceinline__ void full_step(const PointConst &a, uint32_t path, Path<R> &s, JumpCursor<R> &J,
-                                          const KickEntry<R> *kq, const uint32_t *fq, uint32_t qs,
-                                          uint32_t off, R dxi, R h, R hh, R ngam, R A0, R A1, R Fa, R Fb)
+                                          const KickEntry<R> *kq, const JGKick<R> *gq, const uint32_t *fq,
+                                          uint32_t qs, uint32_t wlen, uint32_t off, uint32_t kph, R dxi, R h,
+                                          R hh, R ngam,
+                                          R A0, R A1, R Fa, R Fb)
 {
     R z = R(0);
-    if constexpr ((NOISE & NZ_POISSON) != 0) {
+    if constexpr (queued_kicks<NOISE>()) {
         if (J.nP == off) {                       // Algorithm 3: s <= 0 at this step
             if (J.zP >= R(0)) {
                 z = J.zP;
@@ -91,24 +252,25 @@ __device__ __forceinline__ void full_step(const PointConst &a, uint32_t path, Pa
             }
         }
     }
+    R lev = R(0);
     if constexpr ((NOISE & NZ_DICH) != 0) {
-        const R lev = s.d ? Fb : -Fa;
+        lev = s.d ? Fb : -Fa;
         A0 = A0 + lev;
         A1 = A1 + lev;
     }
-    pc_step<DYN, POT, (NOISE & NZ_POISSON) != 0, R>(s, h, hh, ngam, dxi, z, A0, A1);
+    if constexpr ((NOISE & NZ_JGRID) != 0) {
+        jg_step<R, DYN, POT, NOISE>(a, path, s, J, gq, qs, wlen, off, kph, dxi, h, hh, ngam, A0, A1, lev);
+    } else {
+        pc_step<DYN, POT, (NOISE & NZ_POISSON) != 0, R>(s, h, hh, ngam, dxi, z, A0, A1);
+    }
 }
 
-template <typename R>
-__device__ __forceinline__ R three_point(uint32_t u, R g3)
-{
-    return u < T_MINUS ? -g3 : (u < T_PLUS ? g3 : R(0));
-}
 
 // LDS bytes of the jump queues per lane and path.
 template <typename R, int NOISE> constexpr uint32_t queue_bytes()
 {
-    return (((NOISE & NZ_POISSON) != 0) ? (JCAP + 1) * (uint32_t)sizeof(KickEntry<R>) : 0u) +
+    return (queued_kicks<NOISE>() ? (JCAP + 1) * (uint32_t)sizeof(KickEntry<R>) : 0u) +
+           (((NOISE & NZ_JGRID) != 0) ? JG_CAP * (uint32_t)sizeof(JGKick<R>) : 0u) +
            (((NOISE & NZ_DICH) != 0) ? (JCAP + 1) * 4u : 0u);
 }
 
@@ -128,8 +290,10 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                                               unsigned char *smem, uint32_t qs, uint32_t col0)
 {
     KickEntry<R> *kq = reinterpret_cast<KickEntry<R> *>(smem);
+    JGKick<R> *gq = reinterpret_cast<JGKick<R> *>(smem);       // jump-adapted grid (no fixed-grid queue)
     uint32_t *fq = reinterpret_cast<uint32_t *>(
-        smem + (((NOISE & NZ_POISSON) != 0) ? (JCAP + 1) * qs * sizeof(KickEntry<R>) : 0));
+        smem + (queued_kicks<NOISE>() ? (JCAP + 1) * qs * sizeof(KickEntry<R>) : 0) +
+        (((NOISE & NZ_JGRID) != 0) ? JG_CAP * qs * sizeof(JGKick<R>) : 0));
     JumpCursor<R> J[PPL];
     const R h = (R)a.dt, hh = (R)(0.5 * a.dt), ngam = (R)(-a.gamma), g3 = (R)a.g3;
     const R Fa = (R)a.Fa, Fb = (R)a.Fb;
@@ -144,7 +308,12 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
         const uint32_t wlen = (uint32_t)(wend - n);
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-            if constexpr ((NOISE & NZ_POISSON) != 0) {
+            if constexpr ((NOISE & NZ_JGRID) != 0) {
+                J[j].poff = (uint32_t)s[j].sP;
+                J[j].pth = s[j].thP;
+                jg_window<R, NOISE>(a, path[j], wlen, s[j].kP, J[j], gq + col(j), qs);
+            }
+            if constexpr (queued_kicks<NOISE>()) {
                 kick_window<R>(a, path[j], wlen, (uint32_t)s[j].sP, s[j].kP, kq + col(j), qs);
                 const KickEntry<R> e = kq[col(j)];
                 J[j].nP = e.off;
@@ -183,7 +352,8 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                     normal_pair(hi ? q.z : q.x, hi ? q.w : q.y, zc, zs);
                     dxi = g3 * ((n & 1u) ? zs : zc);
                 }
-                full_step<R, DYN, POT, NOISE>(a, path[j], s[j], J[j], kq + col(j), fq + col(j), qs, off,
+                full_step<R, DYN, POT, NOISE>(a, path[j], s[j], J[j], kq + col(j), gq + col(j), fq + col(j), qs,
+                                              wlen, off, k,
                                               dxi, h, hh, ngam, A0, A1, Fa, Fb);
             }
             k = (k + 1u == a.spp) ? 0u : k + 1u;
@@ -235,8 +405,9 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                             u[j] = times6(u[j]);   // next base-6 digit
                         }
                         if constexpr ((NOISE & NZ_NORMAL) != 0) dxi = g3 * zn[j][dg];
-                        full_step<R, DYN, POT, NOISE>(a, path[j], s[j], J[j], kq + col(j), fq + col(j), qs,
-                                                      off, dxi, h, hh, ngam, A0, A1, Fa, Fb);
+                        full_step<R, DYN, POT, NOISE>(a, path[j], s[j], J[j], kq + col(j), gq + col(j),
+                                                      fq + col(j), qs, wlen, off, k + (uint32_t)(4 * wd + dg), dxi, h, hh, ngam,
+                                                      A0, A1, Fa, Fb);
                     }
                     ++off;
                 }
@@ -252,7 +423,11 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
         // Countdowns at the window end: the next jump lies at or beyond it.
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-            if constexpr ((NOISE & NZ_POISSON) != 0) s[j].sP = (int32_t)(J[j].nP - wlen);
+            if constexpr (queued_kicks<NOISE>()) s[j].sP = (int32_t)(J[j].nP - wlen);
+            if constexpr ((NOISE & NZ_JGRID) != 0) {
+                s[j].sP = (int32_t)(J[j].poff - wlen);
+                s[j].thP = J[j].pth;
+            }
             if constexpr ((NOISE & NZ_DICH) != 0) s[j].sD = (int32_t)(J[j].nD - wlen);
         }
     }
@@ -300,8 +475,15 @@ __device__ __forceinline__ Path<R> init_path(const PointConst &a, uint32_t p)
     s.x = (R)x;
     if (s.x >= (R)L) { s.x -= (R)L; s.w += 1; }   // rounding to the path precision may reach L
     s.v = (DYN == DYN_INERTIAL) ? (R)(a.v0_lo + a.v0_w * ((double)q.y * 0x1p-32)) : R(0);
-    s.sP = 0; s.kP = 0u; s.sD = 0; s.mD = 0u; s.d = 0;
-    if constexpr ((NOISE & NZ_POISSON) != 0) s.sP = (int32_t)floor(expo64(q.z) / a.lam_dt);
+    s.sP = 0; s.kP = 0u; s.sD = 0; s.mD = 0u; s.d = 0; s.thP = 0.0;
+    if constexpr ((NOISE & NZ_JGRID) != 0) {
+        const double T = expo64(q.z) / a.lam_dt;          // first kick time in steps
+        const double Tf = floor(T);
+        s.sP = (int32_t)Tf;
+        s.thP = T - Tf;
+    } else if constexpr ((NOISE & NZ_POISSON) != 0) {
+        s.sP = (int32_t)floor(expo64(q.z) / a.lam_dt);
+    }
     if constexpr ((NOISE & NZ_DICH) != 0) {
         const int32_t dstar = ((double)q.w * 0x1p-32 < a.p_hi) ? 1 : 0;
         s.d = 1 - dstar;
@@ -320,6 +502,7 @@ __global__ void __launch_bounds__(256) k_init(const KArgs a)
     a.w[p] = s.w;
     arr<R>(a.v)[p] = s.v;
     if constexpr ((NOISE & NZ_POISSON) != 0) { a.sP[p] = s.sP; a.kP[p] = s.kP; }
+    if constexpr ((NOISE & NZ_JGRID) != 0) a.thP[p] = s.thP;
     if constexpr ((NOISE & NZ_DICH) != 0) { a.d[p] = s.d; a.sD[p] = s.sD; a.mD[p] = s.mD; }
     if (a.snapshot) { arr<R>(a.xi)[p] = s.x; a.wi[p] = s.w; }
 }

@@ -54,7 +54,9 @@ size_t queue_lds_bytes(uint32_t noise, uint32_t prec, uint32_t ppl, uint32_t blo
 {
     const size_t kick = prec == BM_F32 ? sizeof(KickEntry<float>) : sizeof(KickEntry<double>);
     size_t per = 0;
-    if (noise & BM_NOISE_POISSON) per += (JCAP + 1) * kick;
+    const size_t jg = prec == BM_F32 ? sizeof(JGKick<float>) : sizeof(JGKick<double>);
+    if (noise & BM_NOISE_JUMP_GRID) per += JG_CAP * jg;
+    else if (noise & BM_NOISE_POISSON) per += (JCAP + 1) * kick;
     if (noise & BM_NOISE_DICH) per += (JCAP + 1) * 4;
     return per * ppl * block;
 }
@@ -81,7 +83,7 @@ int check_tune(const bm_tune *t, uint32_t noise, uint32_t prec)
 extern "C" int bm_tune_set_default(uint32_t dyn, uint32_t pot, uint32_t noise, uint32_t prec, const bm_tune *t)
 {
     if (!t) return fail(BM_ERR_INVALID_ARG, "tune must not be NULL");
-    if (dyn > BM_INERTIAL || pot > BM_POT_FREE || (noise & ~7u) || prec > BM_F32)
+    if (dyn > BM_INERTIAL || pot > BM_POT_FREE || (noise & ~31u) || prec > BM_F32)
         return fail(BM_ERR_INVALID_ARG, "unknown model key");
     int rc = check_tune(t, noise, prec);
     if (rc) return rc;
@@ -93,7 +95,7 @@ extern "C" int bm_tune_set_default(uint32_t dyn, uint32_t pot, uint32_t noise, u
 extern "C" int bm_tune_get_default(uint32_t dyn, uint32_t pot, uint32_t noise, uint32_t prec, bm_tune *out)
 {
     if (!out) return fail(BM_ERR_INVALID_ARG, "out must not be NULL");
-    if (dyn > BM_INERTIAL || pot > BM_POT_FREE || (noise & ~7u) || prec > BM_F32)
+    if (dyn > BM_INERTIAL || pot > BM_POT_FREE || (noise & ~31u) || prec > BM_F32)
         return fail(BM_ERR_INVALID_ARG, "unknown model key");
     *out = default_tune(dyn, pot, noise, prec);
     return ok();
@@ -130,8 +132,9 @@ int validate_scan(const bm_model *models, const bm_run *runs, size_t n)
     for (size_t i = 0; i < n; ++i) {
         int rc = validate(&models[i], &runs[i]);
         if (rc) return fail(rc, "point %zu: %s", i, last_error_text());
-        if (models[i].noise & BM_NOISE_NORMAL)
-            return fail(BM_ERR_UNSUPPORTED, "point %zu: the scan runs the three-point scheme only", i);
+        if (models[i].noise & (BM_NOISE_NORMAL | BM_NOISE_JUMP_GRID))
+            return fail(BM_ERR_UNSUPPORTED,
+                        "point %zu: the scan runs the three-point scheme on the fixed grid only", i);
         if (runs[i].n_steps <= runs[i].window_start)
             return fail(BM_ERR_INVALID_ARG, "point %zu: n_steps must exceed window_start", i);
         if (runs[i].n_steps > 0xFFFFFFFFull) return fail(BM_ERR_UNSUPPORTED, "point %zu: n_steps >= 2^32", i);

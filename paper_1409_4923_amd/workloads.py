@@ -13,7 +13,8 @@ import numpy as np
 
 OVERDAMPED, INERTIAL = 0, 1
 POT_SIN, POT_RATCHET, POT_TENT, POT_FREE = 0, 1, 2, 3
-GAUSS, POISSON, DICH, NORMAL = 1, 2, 4, 8   # NORMAL: normal increments, not eq. (25)
+GAUSS, POISSON, DICH, NORMAL, JUMP_GRID = 1, 2, 4, 8, 16   # NORMAL: normal increments, not eq. (25);
+# JUMP_GRID (with POISSON): kicks at their exact times
 F64, F32 = 0, 1
 
 

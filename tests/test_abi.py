@@ -116,7 +116,8 @@ def test_workspace_size_valid_configs():
     ("size", 0, B.BM_ERR_INVALID_ARG),
     ("dyn", 7, B.BM_ERR_INVALID_ARG),
     ("pot", 9, B.BM_ERR_INVALID_ARG),
-    ("noise", 16, B.BM_ERR_INVALID_ARG),
+    ("noise", 32, B.BM_ERR_INVALID_ARG),
+    ("noise", 16, B.BM_ERR_INVALID_ARG),           # jump-adapted grid without Poisson noise
     ("noise", 9, B.BM_ERR_INVALID_ARG),            # three-point and normal increments together
     ("prec", 3, B.BM_ERR_INVALID_ARG),
     ("gamma", 0.0, B.BM_ERR_INVALID_ARG),
@@ -142,6 +143,22 @@ def test_normal_increments_accepted():
         m, r = W.to_c(W.C3.with_(noise=noise, dyn=W.INERTIAL, gamma=0.9))
         rc, _ = _ws_rc(m, r)
         assert rc == B.BM_OK, (noise, B.last_error())
+
+
+def test_jump_grid_accepted_and_limited():
+    for noise in (W.POISSON | W.JUMP_GRID, W.GAUSS | W.POISSON | W.JUMP_GRID,
+                  W.NORMAL | W.POISSON | W.DICH | W.JUMP_GRID):
+        m, r = W.to_c(W.C2.with_(noise=noise))
+        rc, n = _ws_rc(m, r)
+        assert rc == B.BM_OK, (noise, B.last_error())
+        m0, r0 = W.to_c(W.C2)
+        assert n >= _ws_rc(m0, r0)[1] + 8 * W.C2.n_paths    # the FP64 kick phase per path
+    m, r = W.to_c(W.C2.with_(noise=W.POISSON | W.JUMP_GRID, lam=1e4))
+    assert _ws_rc(m, r)[0] == B.BM_ERR_UNSUPPORTED          # more than 16 kicks per step expected
+    pts = W.c4_points(8)
+    M, R = _scan_arrays([pts[0].with_(noise=W.GAUSS | W.POISSON | W.JUMP_GRID, lam=1.0, zeta=0.1)])
+    n = ctypes.c_size_t()
+    assert B.lib().bm_scan_workspace_size(M, R, 1, ctypes.byref(n)) == B.BM_ERR_UNSUPPORTED
 
 
 def test_drive_needs_steps_per_period():

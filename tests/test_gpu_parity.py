@@ -65,8 +65,11 @@ def _model_matrix():
     cases = []
     for dyn in (W.OVERDAMPED, W.INERTIAL):
         for pot in (W.POT_SIN, W.POT_RATCHET, W.POT_TENT, W.POT_FREE):
+            jg = W.POISSON | W.JUMP_GRID
             for noise in list(range(8)) + [W.NORMAL, W.NORMAL | W.POISSON, W.NORMAL | W.DICH,
-                                            W.NORMAL | W.POISSON | W.DICH]:
+                                            W.NORMAL | W.POISSON | W.DICH,
+                                            jg, jg | W.GAUSS, jg | W.DICH, jg | W.GAUSS | W.DICH,
+                                            jg | W.NORMAL, jg | W.NORMAL | W.DICH]:
                 cases.append((dyn, pot, noise))
     return cases
 
@@ -90,7 +93,8 @@ def test_fp64_per_path_model_matrix(dyn, pot, noise):
 
 
 @pytest.mark.parametrize("dyn", [W.OVERDAMPED, W.INERTIAL])
-@pytest.mark.parametrize("noise", [W.POISSON, W.DICH, W.GAUSS | W.POISSON | W.DICH])
+@pytest.mark.parametrize("noise", [W.POISSON, W.DICH, W.GAUSS | W.POISSON | W.DICH,
+                                   W.POISSON | W.JUMP_GRID, W.GAUSS | W.POISSON | W.DICH | W.JUMP_GRID])
 def test_fp64_per_path_high_jump_rates(dyn, noise):
     """Jump rates high enough that lanes exceed the per-window jump queue (lambda dt = 0.25,
     flip probability ~0.2 per step), so later jumps are drawn at their steps."""
@@ -120,7 +124,8 @@ def test_fp32_jump_decisions_equal_fp64_kernel(noise):
     assert np.array_equal(a.noise.numpy(), b.noise.numpy())
 
 
-@pytest.mark.parametrize("w", [W.C2, W.C3], ids=["c2-model", "c3-model"])
+@pytest.mark.parametrize("w", [W.C2, W.C3, W.C2.with_(noise=W.GAUSS | W.POISSON | W.JUMP_GRID)],
+                         ids=["c2-model", "c3-model", "c2-jump-grid"])
 def test_fp64_per_path_jump_models(w):
     w = w.with_(prec=W.F64, n_paths=4096)
     n = 1000
@@ -136,8 +141,9 @@ def test_fp64_per_path_jump_models(w):
 # FP32 paths
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("w", [W.C1, W.C2, W.C3, W.C1.with_(noise=W.NORMAL),
-                               W.C2.with_(noise=W.NORMAL | W.POISSON)],
-                         ids=["c1-model", "c2-model", "c3-model", "c1-normal", "c2-normal"])
+                               W.C2.with_(noise=W.NORMAL | W.POISSON),
+                               W.C2.with_(noise=W.GAUSS | W.POISSON | W.JUMP_GRID)],
+                         ids=["c1-model", "c2-model", "c3-model", "c1-normal", "c2-normal", "c2-jump-grid"])
 def test_fp32_noise_decisions_exact_and_states_close(w):
     w = w.with_(prec=W.F32, n_paths=2048)
     n = 300
@@ -167,7 +173,8 @@ def _ensemble_case(w, n_steps, n_window):
     _ensemble_case(W.C2, 40000, 20000),
     _ensemble_case(W.C3, 100000, 10000),
     _ensemble_case(W.C1.with_(prec=W.F32, noise=W.NORMAL), 20000, 10000),
-], ids=["c1-f32", "c2-f32", "c3-f32", "c1-normal-f32"])
+    _ensemble_case(W.C2.with_(noise=W.GAUSS | W.POISSON | W.JUMP_GRID), 40000, 20000),
+], ids=["c1-f32", "c2-f32", "c3-f32", "c1-normal-f32", "c2-jump-grid-f32"])
 def test_fp32_mean_velocity_within_3se(w):
     say("FP32 <v> vs FP64 oracle: %s, %d paths x %d steps" % (w.name, w.n_paths, w.n_steps))
     e, ps = gpu_run(w, [w.n_steps])
