@@ -40,10 +40,10 @@ FP64_PEAK_FLOPS = 78.6e12
 # reads 0.5 GiB for it: factor 2.0; WRITE_SIZE reads 1 GiB: factor 1.0).  Valid
 # only while the integration kernel's sources hash to KERNEL_SOURCES_SHA256.
 TRAFFIC_WORKLOAD = "inertial-poisson-f32-2^20"
-TRAFFIC_BYTES_PER_LAUNCH = ((10990.0625 + 10497.5) / 2 * 2.0 + (28672.0 + 20480.0) / 2 * 1.0) * 1024
+TRAFFIC_BYTES_PER_LAUNCH = ((10984.6875 + 10494.25) / 2 * 2.0 + (28672.0 + 20480.0) / 2 * 1.0) * 1024
 KERNEL_SOURCES = ("common.hpp", "paths.hpp", "paths_kernels.hpp", "paths_tu.inc", "paths_f32_in.hip",
                   "launch.hpp")
-KERNEL_SOURCES_SHA256 = "5576f54df932629b9d0d672e0162be676b84135afc56e543e3a7b4b695b0b1e9"
+KERNEL_SOURCES_SHA256 = "6a5142299c3746af04415db5d5f438f88db11fe8253e7095617a673eb11734b7"
 
 
 def algorithmic_work(w):
