@@ -137,6 +137,17 @@ def oracle_baseline(w, seconds: float, threads: int):
                 mean_v=s.mean, se=s.se, n_paths=S)
 
 
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def scan_leg(args):
     """Batched scan of the 4096-point inertial workload: autotune on short horizons,
     then one graph launch timed with HIP events on the plan's stream."""
@@ -446,6 +457,11 @@ def main():
         rec["oracle_se_v"] = cb["se"]
         rec["mean_v_within_3se"] = abs(st.mean - cb["mean_v"]) <= 3 * math.hypot(st.se, cb["se"])
         rec["speedup_vs_oracle"] = value / cb["value"]
+        # the paper's GPU/CPU figure is against one CPU core
+        one = oracle_baseline(w, args.cpu_seconds / 4, 1)
+        rec["cpu_baseline"]["single_core"] = {"value": one["value"], "sample": one["sample"]}
+        rec["cpu_baseline"]["host_cpu"] = host_cpu_model()
+        rec["speedup_vs_one_core"] = value / one["value"]
     legs = [l for l in args.legs.split(",") if l and l != "none"]
     if "scan" in legs:
         rec["scan"] = scan_leg(args)

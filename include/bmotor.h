@@ -163,6 +163,20 @@ int bm_ensemble_workspace_size(const bm_model *model, const bm_run *run, size_t 
 int bm_ensemble_create(const bm_model *model, const bm_run *run, void *d_ws, size_t ws_bytes,
                        void *stream, bm_ensemble **out);
 
+/* Checkpoint / resume.  The caller-owned workspace holds the whole state of an
+ * ensemble (positions, velocities, window snapshot, jump countdowns and counts,
+ * per-path velocities); the handle holds only host metadata and the step count
+ * bm_ensemble_steps reports.  A checkpoint is therefore a byte copy of the
+ * workspace (device or host) taken after the stream has completed, plus that
+ * step count.  bm_ensemble_attach opens a handle on such a workspace (d_ws,
+ * 256-byte aligned, >= bm_ensemble_workspace_size bytes) without touching the
+ * path state: integrating from there gives bit for bit what an uninterrupted run
+ * gives (the random streams are counter-based).  model and run must equal those
+ * the workspace was created with -- the library cannot check this.  Uploads the
+ * drive table like bm_ensemble_create (and synchronises `stream`). */
+int bm_ensemble_attach(const bm_model *model, const bm_run *run, void *d_ws, size_t ws_bytes,
+                       uint64_t steps_done, void *stream, bm_ensemble **out);
+
 /* Release the handle (host metadata only; the workspace stays the caller's). */
 int bm_ensemble_destroy(bm_ensemble *e);
 

@@ -75,6 +75,7 @@ SIGNATURES = [
     ("bm_last_error", ctypes.c_char_p, []),
     ("bm_ensemble_workspace_size", ctypes.c_int, [_P(bm_model), _P(bm_run), _P(_sz)]),
     ("bm_ensemble_create", ctypes.c_int, [_P(bm_model), _P(bm_run), _vp, _sz, _vp, _P(_vp)]),
+    ("bm_ensemble_attach", ctypes.c_int, [_P(bm_model), _P(bm_run), _vp, _sz, ctypes.c_uint64, _vp, _P(_vp)]),
     ("bm_ensemble_destroy", ctypes.c_int, [_vp]),
     ("bm_ensemble_set_tune", ctypes.c_int, [_vp, _P(bm_tune)]),
     ("bm_integrate", ctypes.c_int, [_vp, ctypes.c_uint64]),
@@ -179,6 +180,14 @@ def bm_ensemble_create(model: bm_model, run: bm_run, d_ws: int, ws_bytes: int, s
     return int(h.value)
 
 
+def bm_ensemble_attach(model: bm_model, run: bm_run, d_ws: int, ws_bytes: int, steps_done: int,
+                       stream: int) -> int:
+    h = ctypes.c_void_p()
+    check(lib().bm_ensemble_attach(ctypes.byref(model), ctypes.byref(run), d_ws, ws_bytes, steps_done, stream,
+                                   ctypes.byref(h)))
+    return int(h.value)
+
+
 def bm_ensemble_destroy(h: int) -> None:
     check(lib().bm_ensemble_destroy(h))
 
@@ -224,17 +233,33 @@ class PathState:
 class Ensemble:
     """An ensemble of paths living in a torch-allocated workspace on the current GPU."""
 
-    def __init__(self, model: bm_model, run: bm_run, tune: bm_tune | None = None, device=None):
+    def __init__(self, model: bm_model, run: bm_run, tune: bm_tune | None = None, device=None,
+                 checkpoint=None):
+        """checkpoint: (workspace bytes as a uint8 tensor, steps done) from `checkpoint()`;
+        the ensemble then resumes from that state instead of drawing initial conditions."""
         import torch
         self.torch = torch
         self.device = torch.device("cuda") if device is None else torch.device(device)
         self.model, self.run = model, run
         self.ws_bytes = bm_ensemble_workspace_size(model, run)
-        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
-        self.h = bm_ensemble_create(model, run, self.ws.data_ptr(), self.ws_bytes, self.stream.cuda_stream)
+        if checkpoint is None:
+            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+            self.h = bm_ensemble_create(model, run, self.ws.data_ptr(), self.ws_bytes, self.stream.cuda_stream)
+        else:
+            data, steps = checkpoint
+            if data.dtype != torch.uint8 or data.numel() != self.ws_bytes:
+                raise ValueError("checkpoint holds %d bytes, this ensemble needs %d" % (data.numel(), self.ws_bytes))
+            self.ws = data.to(self.device).contiguous().clone()
+            self.h = bm_ensemble_attach(model, run, self.ws.data_ptr(), self.ws_bytes, int(steps),
+                                        self.stream.cuda_stream)
         if tune is not None:
             bm_ensemble_set_tune(self.h, tune)
+
+    def checkpoint(self, device="cpu"):
+        """(copy of the workspace, steps done): the whole state of the ensemble."""
+        self.stream.synchronize()
+        return self.ws.to(device, copy=True), self.steps
 
     def close(self):
         if getattr(self, "h", None):

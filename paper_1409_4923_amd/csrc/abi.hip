@@ -318,12 +318,15 @@ static void fill_table(bm_ensemble *e)
     e->tab32.assign(e->tab64.begin(), e->tab64.end());
 }
 
-extern "C" int bm_ensemble_create(const bm_model *model, const bm_run *run, void *d_ws,
-                                  size_t ws_bytes, void *stream, bm_ensemble **out)
+// Creates the handle and uploads the drive table; `init` enqueues the initial
+// conditions, otherwise the workspace already holds the state after steps_done.
+static int open_ensemble(const bm_model *model, const bm_run *run, void *d_ws, size_t ws_bytes, void *stream,
+                         bool init, uint64_t steps_done, bm_ensemble **out)
 {
     int rc = validate(model, run);
     if (rc) return rc;
     if (!out) return fail(BM_ERR_INVALID_ARG, "out must not be NULL");
+    if (steps_done > 0xFFFFFFFFull) return fail(BM_ERR_UNSUPPORTED, "total step count must stay below 2^32");
     const Layout L = layout(model, run);
     if (!d_ws || ((uintptr_t)d_ws & 255u)) return fail(BM_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
     if (ws_bytes < L.total) return fail(BM_ERR_WORKSPACE, "workspace %zu B < %zu B needed", ws_bytes, L.total);
@@ -338,7 +341,7 @@ extern "C" int bm_ensemble_create(const bm_model *model, const bm_run *run, void
     e->lay = L;
     e->ws = (char *)d_ws;
     e->stream = (hipStream_t)stream;
-    e->n_done = 0;
+    e->n_done = steps_done;
     const bm_tune dt = default_tune(model->dyn, model->pot, model->noise, run->prec);
     e->ppl = dt.paths_per_lane;
     e->block = dt.block;
@@ -349,23 +352,37 @@ extern "C" int bm_ensemble_create(const bm_model *model, const bm_run *run, void
     const void *src = f32 ? (const void *)e->tab32.data() : (const void *)e->tab64.data();
     const size_t tb = (f32 ? 4 : 8) * e->tab64.size();
     // The table is read from host memory owned by the handle: wait for the copy so
-    // that the handle can be destroyed at any time after create returns.
+    // that the handle can be destroyed at any time after this returns.
     hipError_t he = hipMemcpyAsync((char *)d_ws + L.tab, src, tb, hipMemcpyHostToDevice, e->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(e->stream);
     if (he != hipSuccess) { delete e; return hip_fail(he, "drive table upload"); }
 
-    KArgs k = e->k;
-    k.snapshot = run->window_start == 0 ? 1u : 0u;
-    const int pot = (int)model->pot, noise = (int)model->noise;
-    if (f32)
-        he = model->dyn == BM_INERTIAL ? launch_init_f32_in(pot, noise, k, e->stream)
-                                       : launch_init_f32_od(pot, noise, k, e->stream);
-    else
-        he = model->dyn == BM_INERTIAL ? launch_init_f64_in(pot, noise, k, e->stream)
-                                       : launch_init_f64_od(pot, noise, k, e->stream);
-    if (he != hipSuccess) { delete e; return hip_fail(he, "init kernel launch"); }
+    if (init) {
+        KArgs k = e->k;
+        k.snapshot = run->window_start == 0 ? 1u : 0u;
+        const int pot = (int)model->pot, noise = (int)model->noise;
+        if (f32)
+            he = model->dyn == BM_INERTIAL ? launch_init_f32_in(pot, noise, k, e->stream)
+                                           : launch_init_f32_od(pot, noise, k, e->stream);
+        else
+            he = model->dyn == BM_INERTIAL ? launch_init_f64_in(pot, noise, k, e->stream)
+                                           : launch_init_f64_od(pot, noise, k, e->stream);
+        if (he != hipSuccess) { delete e; return hip_fail(he, "init kernel launch"); }
+    }
     *out = e;
     return ok();
+}
+
+extern "C" int bm_ensemble_create(const bm_model *model, const bm_run *run, void *d_ws,
+                                  size_t ws_bytes, void *stream, bm_ensemble **out)
+{
+    return open_ensemble(model, run, d_ws, ws_bytes, stream, true, 0, out);
+}
+
+extern "C" int bm_ensemble_attach(const bm_model *model, const bm_run *run, void *d_ws, size_t ws_bytes,
+                                  uint64_t steps_done, void *stream, bm_ensemble **out)
+{
+    return open_ensemble(model, run, d_ws, ws_bytes, stream, false, steps_done, out);
 }
 
 extern "C" int bm_ensemble_destroy(bm_ensemble *e)

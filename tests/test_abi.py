@@ -210,6 +210,21 @@ def test_create_checks_workspace_then_device():
         assert h.value is None
 
 
+def test_attach_checks_arguments_before_device():
+    m, r = W.to_c(W.C2)
+    L = B.lib()
+    h = ctypes.c_void_p()
+    need = B.bm_ensemble_workspace_size(m, r)
+    assert L.bm_ensemble_attach(ctypes.byref(m), ctypes.byref(r), 0x10000, need, 1 << 32, None,
+                                ctypes.byref(h)) == B.BM_ERR_UNSUPPORTED
+    assert L.bm_ensemble_attach(ctypes.byref(m), ctypes.byref(r), 0x1001, need, 10, None,
+                                ctypes.byref(h)) == B.BM_ERR_WORKSPACE
+    assert L.bm_ensemble_attach(ctypes.byref(m), ctypes.byref(r), 0x10000, need - 256, 10, None,
+                                ctypes.byref(h)) == B.BM_ERR_WORKSPACE
+    assert L.bm_ensemble_attach(ctypes.byref(m), ctypes.byref(r), 0x10000, need, 10, None,
+                                None) == B.BM_ERR_INVALID_ARG
+
+
 # ---------------------------------------------------------------------------
 # Scan entry points (no device calls)
 # ---------------------------------------------------------------------------

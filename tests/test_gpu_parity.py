@@ -359,3 +359,32 @@ def test_density_histogram(prec):
         assert np.array_equal(got, ref)
     else:
         assert np.max(np.abs(got - ref)) <= 0.02 * ref.max() + 20
+
+
+@pytest.mark.parametrize("w", [W.C2.with_(n_paths=3000, n_steps=5000, n_window=2000),
+                               W.C3.with_(n_paths=3000, n_steps=5000, n_window=1000, prec=W.F64),
+                               W.C2.with_(n_paths=3000, n_steps=5000, n_window=2000,
+                                          noise=W.GAUSS | W.POISSON | W.JUMP_GRID)],
+                         ids=["c2-f32", "c3-f64", "c2-jump-grid"])
+def test_checkpoint_resume_bit_identical(w):
+    """A checkpoint (host copy of the workspace + step count) resumed by bm_ensemble_attach,
+    before and after the window start, gives what an uninterrupted run gives, bit for bit."""
+    m, r = W.to_c(w)
+    ref = B.Ensemble(m, r)
+    ref.integrate(w.n_steps)
+    a = ref.read()
+    for cut in (1500, 3333):
+        e = B.Ensemble(m, r)
+        e.integrate(cut)
+        ck = e.checkpoint()
+        e.close()
+        del e
+        f = B.Ensemble(m, r, checkpoint=ck)
+        assert f.steps == cut
+        f.integrate(w.n_steps - cut)
+        b = f.read()
+        assert np.array_equal(a.x.numpy(), b.x.numpy()) and np.array_equal(a.v.numpy(), b.v.numpy())
+        assert np.array_equal(a.noise.numpy(), b.noise.numpy())
+        assert np.array_equal(a.vp.numpy(), b.vp.numpy(), equal_nan=True)
+        sa, sb = ref.stats(), f.stats()
+        assert (sa.mean, sa.se, sa.n) == (sb.mean, sb.se, sb.n)
