@@ -21,7 +21,6 @@ static_assert(IN == BM_MLP_INPUTS && H == BM_MLP_HIDDEN, "shape differs from bmo
 
 namespace {
 
-constexpr uint64_t CHUNK = 65536;       // inference rows per pass (bounds the workspace)
 
 // ---------------------------------------------------------------------------
 // Small layers
@@ -312,13 +311,15 @@ struct MlpLayout {
 MlpLayout mlp_layout(uint32_t nm, uint64_t batch, bool training)
 {
     MlpLayout L{};
-    const uint64_t R = training ? batch : (batch < CHUNK ? batch : CHUNK);
+    const uint64_t R = batch;
     L.rows = R;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o += up(bytes); return at; };
-    L.a1 = take(nm * R * H * 2);
-    L.a2 = take(nm * R * H * 2);
-    L.a3 = take(nm * R * H * 2);
+    if (training) {                    // inference keeps its activations in registers
+        L.a1 = take(nm * R * H * 2);
+        L.a2 = take(nm * R * H * 2);
+        L.a3 = take(nm * R * H * 2);
+    }
     L.y = take(nm * batch * 4);
     if (training) {
         L.u = take(nm * R * IN * 4);
@@ -368,6 +369,150 @@ GemmArgs gemm_args()
 }
 
 // Forward of `rows` rows through all members; y[m * y_stride + y_off + r].
+// ---------------------------------------------------------------------------
+// Fused inference: one work-group runs 128 rows of one member through all four
+// layers; activations never leave the registers.  The 256 x 256 layers are
+// computed transposed, Z^T = W A^T, with W as the MFMA A operand (staged through
+// LDS one 16-row tile at a time, double-buffered) and the activations as the B
+// operand: a 16 x 16 output tile leaves lane (g = lane/16, c = lane%16) holding
+// features 4g..4g+3 of row c, which is exactly the B-operand slot of the next
+// layer if its contraction index is permuted -- k-step s, slot j of lane group g
+// stands for feature 32 s + 4 g + j (j < 4) or 32 s + 16 + 4 g + (j - 4) (j >= 4),
+// and the W fragments are read from LDS in that order.
+// ---------------------------------------------------------------------------
+constexpr int FROWS = 128;             // rows per work-group: 4 waves x 2 tiles of 16
+constexpr int FLDS = H + 8;            // padded row of a staged W tile (bf16)
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __bf16 to_bf(float f) { return (__bf16)f; }   // v_cvt_pk_bf16_f32 (RNE)
+
+__device__ __forceinline__ int perm_feature(int s, int g, int j)
+{
+    return 32 * s + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
+}
+
+__global__ void __launch_bounds__(256) k_mlp_infer(const float *x, uint64_t rows, const bf16_t *wbf,
+                                                   const float *params, float *y, uint64_t y_stride)
+{
+    __shared__ __align__(16) bf16_t sW[3][16 * FLDS];
+    __shared__ __align__(16) float sL1[H * 8];          // per feature: W1[f][0..4], b1[f], pad
+    __shared__ float sB[2][H], sW4[H];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, c = lane & 15;
+    const int m = blockIdx.y;
+    const float *P = params + (uint64_t)m * NPARAM;
+    const bf16_t *WB = wbf + (uint64_t)m * NBF;
+#pragma unroll
+    for (int j = 0; j < IN; ++j) sL1[t * 8 + j] = bf2f(WB[BOFF_W1 + t * IN + j]);
+    sL1[t * 8 + 5] = P[OFF_B1 + t];
+    sB[0][t] = P[OFF_B2 + t];
+    sB[1][t] = P[OFF_B3 + t];
+    sW4[t] = bf2f(WB[BOFF_W4 + t]);
+
+    // staging of W tile ft (rows 16 ft .. 16 ft + 15, all 256 k): thread t moves 32 B
+    const int st_row = t >> 4, st_k = (t & 15) * 16;
+    auto load_tile = [&](const bf16_t *W, int ft, uint4 &v0, uint4 &v1) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(W + (uint64_t)(16 * ft + st_row) * H + st_k);
+        v0 = src[0];
+        v1 = src[1];
+    };
+    auto store_tile = [&](int buf, const uint4 &v0, const uint4 &v1) {
+        uint4 *dst = reinterpret_cast<uint4 *>(&sW[buf][st_row * FLDS + st_k]);
+        dst[0] = v0;
+        dst[1] = v1;
+    };
+    uint4 p0, p1;
+    load_tile(WB + BOFF_W2, 0, p0, p1);
+    store_tile(0, p0, p1);
+    load_tile(WB + BOFF_W2, 1, p0, p1);
+    store_tile(1, p0, p1);
+    __syncthreads();
+
+    // ---- layer 1 (5 -> 256, FP32 FMA on the BF16 weights) into B operands ----
+    const uint64_t base = (uint64_t)blockIdx.x * FROWS + (uint64_t)wave * 32;
+    bf16x8 act[2][8];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        const uint64_t r = base + 16 * rt + c;
+        float u[IN];
+        normalise(x + (r < rows ? r : 0) * IN, u);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float *w = &sL1[perm_feature(s, g, j) * 8];
+                float z = w[5];
+#pragma unroll
+                for (int i = 0; i < IN; ++i) z = fmaf(w[i], u[i], z);
+                act[rt][s][j] = to_bf(gelu(z));
+            }
+        }
+    }
+
+    // ---- layers 2 and 3 on MFMA ----
+    // Software pipeline over the 32 W tiles of the two layers (tile T: layer T / 16,
+    // output rows 16 (T % 16) ..): the MFMAs of tile T + 1 are issued before the
+    // GELU epilogue of tile T, so matrix cores and VALU overlap.  Tile T lives in LDS
+    // buffer T % 3; tile T + 2 is fetched from global memory during iteration T and
+    // stored after its epilogue into the buffer tile T - 1 used, which every wave
+    // finished reading before the barrier that ended iteration T - 2.  One barrier
+    // per iteration also publishes tile T + 2 before iteration T + 1 reads it.
+    auto mma_tile = [&](int buf, floatx4 (&acc)[2]) {
+        acc[0] = floatx4{0.f, 0.f, 0.f, 0.f};
+        acc[1] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const bf16_t *wrow = &sW[buf][c * FLDS];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const bf16x4 lo = *reinterpret_cast<const bf16x4 *>(wrow + 32 * s + 4 * g);
+            const bf16x4 hi = *reinterpret_cast<const bf16x4 *>(wrow + 32 * s + 16 + 4 * g);
+            const bf16x8 a = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[rt][s], acc[rt], 0, 0, 0);
+        }
+    };
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+        bf16x8 nxt[2][8];
+        floatx4 acc[2][2];
+        mma_tile((16 * layer) % 3, acc[0]);
+#pragma unroll
+        for (int ft = 0; ft < 16; ++ft) {
+            const int T = 16 * layer + ft;
+            if (T + 2 < 32) load_tile(WB + ((T + 2) < 16 ? BOFF_W2 : BOFF_W3), (T + 2) & 15, p0, p1);
+            if (ft + 1 < 16) mma_tile((T + 1) % 3, acc[(ft + 1) & 1]);
+            // epilogue of tile T: acc[rt][i] = Z^T[16 ft + 4 g + i][row c of tile rt]
+            // -> next layer's slot (k-step ft / 2, j = 4 (ft % 2) + i)
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    nxt[rt][ft >> 1][4 * (ft & 1) + i] =
+                        to_bf(gelu(acc[ft & 1][rt][i] + sB[layer][16 * ft + 4 * g + i]));
+            if (T + 2 < 32) store_tile((T + 2) % 3, p0, p1);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int s = 0; s < 8; ++s) act[rt][s] = nxt[rt][s];
+    }
+
+    // ---- layer 4 (256 -> 1): partial dot per lane group, then across the 4 groups ----
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        float sum = 0.0f;
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sum = fmaf((float)act[rt][s][j], sW4[perm_feature(s, g, j)], sum);
+        sum += __shfl_xor(sum, 16, 64);
+        sum += __shfl_xor(sum, 32, 64);
+        const uint64_t r = base + 16 * rt + c;
+        if (g == 0 && r < rows) y[(uint64_t)m * y_stride + r] = sum + P[OFF_B4];
+    }
+}
+
 hipError_t forward_pass(uint32_t nm, const float *params, const bf16_t *wbf, const float *x, const uint32_t *idx,
                         uint64_t idx_stride, uint64_t row0, int rows, char *ws, const MlpLayout &L, bool training,
                         float *y, uint64_t y_stride, uint64_t y_off, hipStream_t s)
@@ -462,13 +607,10 @@ extern "C" int bm_mlp_forward(uint32_t n_members, const float *d_params, const u
     rc = check_device(&dev);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    for (uint64_t r0 = 0; r0 < batch; r0 += L.rows) {
-        const int rows = (int)(batch - r0 < L.rows ? batch - r0 : L.rows);
-        hipError_t e = forward_pass(n_members, d_params, (const bf16_t *)d_wbf, d_x, nullptr, 0, r0, rows,
-                                    (char *)d_ws, L, false, d_y, batch, r0, s);
-        if (e != hipSuccess) return hip_fail(e, "bm_mlp_forward");
-    }
-    return ok();
+    hipLaunchKernelGGL(k_mlp_infer, dim3((uint32_t)((batch + FROWS - 1) / FROWS), n_members), dim3(256), 0, s, d_x,
+                       batch, (const bf16_t *)d_wbf, d_params, d_y, batch);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ok() : hip_fail(e, "bm_mlp_forward");
 }
 
 extern "C" int bm_mlp_backward(uint32_t n_members, const float *d_params, const uint16_t *d_wbf, const float *d_x,
@@ -586,12 +728,9 @@ extern "C" int bm_surrogate_query(uint32_t n_members, const float *d_params, con
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)d_ws;
     float *y = (float *)(ws + L.y);
-    hipError_t e = hipSuccess;
-    for (uint64_t r0 = 0; r0 < batch && e == hipSuccess; r0 += L.rows) {
-        const int rows = (int)(batch - r0 < L.rows ? batch - r0 : L.rows);
-        e = forward_pass(n_members, d_params, (const bf16_t *)d_wbf, d_x, nullptr, 0, r0, rows, ws, L, false, y,
-                         batch, r0, s);
-    }
+    hipLaunchKernelGGL(k_mlp_infer, dim3((uint32_t)((batch + FROWS - 1) / FROWS), n_members), dim3(256), 0, s, d_x,
+                       batch, (const bf16_t *)d_wbf, d_params, y, batch);
+    hipError_t e = hipGetLastError();
     const uint64_t nblk = (batch + 255) / 256;
     uint32_t *blk = (uint32_t *)(ws + L.blk);
     if (e == hipSuccess) {

@@ -44,13 +44,17 @@ __device__ __forceinline__ bf16_t f2bf(float f)
 }
 __device__ __forceinline__ float bf2f(bf16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-// tanh-GELU: 0.5 z (1 + tanh(c (z + 0.044715 z^3))), c = sqrt(2 / pi)
+// tanh-GELU: 0.5 z (1 + tanh u), u = c (z + 0.044715 z^3), c = sqrt(2 / pi).
+// Since 0.5 (1 + tanh u) = 1 / (1 + e^{-2u}), gelu = z sigma with
+// sigma = 1 / (1 + 2^{-2 c log2(e) z (1 + 0.044715 z^2)}) on the hardware exp2 and
+// reciprocal (1 ulp each); sigma saturates to 0 / 1 for large |u|.  t = tanh u.
 __device__ __forceinline__ float gelu_t(float z, float &t)
 {
-    const float c = 0.7978845608028654f;
-    const float u = c * fmaf(0.044715f * z, z * z, z);
-    t = 1.0f - 2.0f / (__expf(2.0f * u) + 1.0f);         // tanh(u), saturates correctly
-    return 0.5f * z * (1.0f + t);
+    const float k = -2.0f * 0.7978845608028654f * 1.4426950408889634f;   // -2 c log2(e)
+    const float w = z * fmaf(k * 0.044715f, z * z, k);
+    const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(w));
+    t = fmaf(2.0f, sg, -1.0f);
+    return z * sg;
 }
 __device__ __forceinline__ float gelu(float z)
 {
