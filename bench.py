@@ -40,67 +40,82 @@ FP64_PEAK_FLOPS = 78.6e12
 # reads 0.5 GiB for it: factor 2.0; WRITE_SIZE reads 1 GiB: factor 1.0).  Valid
 # only while the integration kernel's sources hash to KERNEL_SOURCES_SHA256.
 TRAFFIC_WORKLOAD = "inertial-poisson-f32-2^20"
-TRAFFIC_BYTES_PER_LAUNCH = ((10984.6875 + 10494.25) / 2 * 2.0 + (28672.0 + 20480.0) / 2 * 1.0) * 1024
+TRAFFIC_BYTES_PER_LAUNCH = ((10987.5625 + 10498.0) / 2 * 2.0 + (28672.0 + 20480.0) / 2 * 1.0) * 1024
 KERNEL_SOURCES = ("common.hpp", "paths.hpp", "paths_kernels.hpp", "paths_tu.inc", "paths_f32_in.hip",
                   "launch.hpp")
-KERNEL_SOURCES_SHA256 = "6a5142299c3746af04415db5d5f438f88db11fe8253e7095617a673eb11734b7"
+KERNEL_SOURCES_SHA256 = "c33c2ccd61b5083ff7c2ad23dd25248a7103e54e2b76587eefa883bad4cd057c"
 
 
 def algorithmic_work(w):
-    """(VALU lane-ops, transcendental lane-ops, flops) the method needs per path-step.
+    """(main-pipe VALU lane-ops, transcendental lane-ops, flops) per path-step.
 
-    Counted from Algorithms 1-4 in their cheapest direct form, one op per add,
-    multiply, FMA, compare, select or conversion; transcendentals (cos, log) are
-    counted apart because they issue to their own unit.  Flops count an FMA as 2
-    and a transcendental as 1.  Philox4x32-10 = 10 rounds x (2 wide products + 2
-    three-way xors) = 40 ops, amortised over 16 steps (Algorithm 2) or 2 kicks /
-    4 flips (Algorithms 3 / 4).
+    The cheapest direct form of Algorithms 1-4 (one op per add, multiply, FMA,
+    compare, select or conversion; transcendentals -- cos, log, sqrt, sin -- apart,
+    as they issue to their own unit; flops count an FMA as 2):
+      drift evaluation (3 per step): V = sin 2 pi x: cos, 1 FMA; ratchet: cos, 2 FMA;
+        tent: mul, floor, FMA, compare, select, add; inertial: + 1 FMA (-gamma v);
+      Algorithm 1: inertial 6 FMA + 5 adds, overdamped 3 FMA + 3 adds (the noise
+        increment is added once), + 1 add for a kick;
+      dichotomous level: 1 select + 2 adds; fold: 4 ops per 16 steps;
+      Algorithm 2 (three-point): 2 compares + 2 selects + 2 shifts for the next
+        base-6 digit + Philox4x32-10 (10 rounds x (2 wide products + 2 three-way
+        xors) = 40 ops) per 16 steps;  normal increments: Philox per 4 steps,
+        Box-Muller (8 ops + log, sqrt, cos, sin per pair) and the scale;
+      Algorithm 3: 1 compare per step; per kick half a Philox block (20), the FP32
+        countdown (8), the amplitude (4 + log), queue write and read (4);
+      Algorithm 4: 1 compare per step; per flip a quarter block (10), countdown (8 +
+        log), state flip (1), queue write and read (3).
+    The jump-adapted grid adds, per kick, a Philox block for the piece increment (40 /
+    16 or 40 / 4), the FP64 kick time (log, divide: ~30), the drive inside the step
+    (3 + cos) and a second Algorithm 1 piece.
     """
     from paper_1409_4923_amd import workloads as W
     ops = trans = flops = 0.0
     inertial = w.dyn == W.INERTIAL
-    # drift evaluations (3 per step): potential force + drive + friction
     if w.pot == W.POT_SIN:
-        per_eval_ops, per_eval_trans, per_eval_flops = 1, 1, 3     # cos | fma(-2 pi, c, A')
+        e_ops, e_tr, e_fl = 1, 1, 3
     elif w.pot == W.POT_RATCHET:
-        per_eval_ops, per_eval_trans, per_eval_flops = 3, 1, 5     # cos | add, mul, fma
+        e_ops, e_tr, e_fl = 2, 1, 5
     elif w.pot == W.POT_TENT:
-        per_eval_ops, per_eval_trans, per_eval_flops = 4, 0, 2     # mul, floor, fma, cmp/select
+        e_ops, e_tr, e_fl = 6, 0, 4
     else:
-        per_eval_ops, per_eval_trans, per_eval_flops = 0, 0, 0
+        e_ops, e_tr, e_fl = 0, 0, 0
     if inertial:
-        per_eval_ops += 1                                        # fma(-gamma, v, f)
-        per_eval_flops += 2
-    ops += 3 * per_eval_ops
-    trans += 3 * per_eval_trans
-    flops += 3 * per_eval_flops
-    # constant-within-step forcing A' = A(t) + level - bias at t_n and t_{n+1}
-    if w.noise & (W.POISSON | W.DICH):
-        ops += 2
-        flops += 2
-    # predictor / corrector updates
+        e_ops, e_fl = e_ops + 1, e_fl + 2
+    ops += 3 * e_ops
+    trans += 3 * e_tr
+    flops += 3 * e_fl + 3 * e_tr
+    kick = (w.noise & W.POISSON) != 0
     if inertial:
-        ops += 14                                     # 6 fma + 8 add
-        flops += 20
+        ops += 11 + (1 if kick else 0)
+        flops += 17 + (1 if kick else 0)
     else:
-        ops += 9                                      # 3 fma + 6 add
-        flops += 12
-    # fold: floor, sub, convert, integer add
-    ops += 4
-    flops += 2
+        ops += 6 + (1 if kick else 0)
+        flops += 9 + (1 if kick else 0)
+    ops += 4.0 / 16.0
+    flops += 2.0 / 16.0
     if w.noise & W.GAUSS:
-        ops += 5 + 40.0 / 16.0                        # 2 compares, 2 selects, digit shift
-    p_kick = -math.expm1(-w.lam * w.step()) if (w.noise & W.POISSON) else 0.0
-    if w.noise & W.POISSON:
-        ops += 2 + p_kick * (40.0 / 2.0 + 8.0)        # countdown; kick: draws, floor, scaling
-        trans += p_kick * 2.0                         # two logs per kick
-        flops += p_kick * 2.0
+        ops += 6 + 40.0 / 16.0
+    if w.noise & W.NORMAL:
+        ops += 40.0 / 4.0 + 4 + 1
+        trans += 2
+        flops += 4
+    h = w.step()
+    if kick:
+        p_kick = -math.expm1(-w.lam * h)
+        ops += 1 + p_kick * (20 + 8 + 4 + 4)
+        trans += p_kick * 2
+        flops += p_kick * 6
+        if w.noise & W.JUMP_GRID:
+            piece = 40.0 / 16.0 + 6 if (w.noise & W.GAUSS) else (40.0 / 4.0 + 5 if (w.noise & W.NORMAL) else 0)
+            ops += p_kick * (piece + 30 + 3 + (11 if inertial else 6) + 3 * e_ops)
+            trans += p_kick * (1 + 3 * e_tr)
+            flops += p_kick * (20 + (17 if inertial else 9) + 3 * e_fl)
     if w.noise & W.DICH:
-        p_flip = max(-math.expm1(-w.mua * w.step()), -math.expm1(-w.mub * w.step()))
-        ops += 3 + p_flip * (40.0 / 4.0 + 5.0)        # countdown + level select; flip draw
-        trans += p_flip                               # one log per flip
-        flops += p_flip
-    flops += 3 * per_eval_trans
+        p_flip = max(-math.expm1(-w.mua * h), -math.expm1(-w.mub * h))
+        ops += 3 + 1 + p_flip * (10 + 8 + 1 + 3)
+        trans += p_flip
+        flops += 2 + p_flip
     return ops, trans, flops
 
 

@@ -132,8 +132,8 @@ template <int POT, typename R> __device__ __forceinline__ void fold(Path<R> &s)
 // offset with the next queued offset.  A lane with more than JCAP jumps in a
 // window queues an "inline" marker and draws the rest at their steps.
 // ---------------------------------------------------------------------------
-constexpr uint32_t JW = 128;          // jump window, a multiple of 16 steps
-constexpr uint32_t JCAP = 8;          // queued jumps per lane and window
+constexpr uint32_t JW = 256;          // jump window, a multiple of 16 steps
+constexpr uint32_t JCAP = 11;         // queued jumps per lane and window
 constexpr uint32_t INLINE_BIT = 0x80000000u;
 
 // A kick of the jump-adapted grid, drawn ahead: its step offset in the window, the
@@ -144,7 +144,10 @@ template <typename R> struct JGKick {
     R th, z, u;
 };
 constexpr uint32_t JG_NONE = 0xFFFFFFFFu;
-constexpr uint32_t JG_CAP = 6;     // queued kicks per lane and window (Poisson(2) exceeds 6 w.p. 0.5%)
+// Queued kicks per lane and window of the jump-adapted grid (more are drawn at their
+// steps): 10 in FP32, 6 in FP64, so that the FP64 queues of 256 lanes with the
+// dichotomous queue still fit in 64 KiB of LDS.
+template <typename R> constexpr uint32_t jg_cap() { return sizeof(R) == 4 ? 10u : 6u; }
 
 template <typename R> struct KickEntry {
     uint32_t off;   // step offset in the window (>= window length: none left)
@@ -156,7 +159,10 @@ template <typename R> struct KickEntry {
 // an FP32 estimate X32 with v_log_f32; its error is below
 // 3e-7 / (rate dt) + 4.2e-7 X (rounding of 1 - phi, log2 near 1, the scale), and
 // the tolerance tol0 + tol1 X is several times that, so floor(X32) is exact
-// unless X32 lies within the tolerance of an integer -- then FP64 decides.
+// unless X32 lies within the tolerance of an integer -- then FP64 decides.  The
+// FP64 work sits behind a wave-uniform branch taken only when some lane needs it
+// (a few per cent of the draws); as a plain per-lane branch the compiler turns it
+// into a select and evaluates the FP64 log and divide for every draw.
 template <typename R>
 __device__ __forceinline__ uint32_t countdown(uint32_t w, double rate_dt, float c, float tol0, float tol1)
 {
@@ -166,7 +172,13 @@ __device__ __forceinline__ uint32_t countdown(uint32_t w, double rate_dt, float 
         const float fl = floorf(X);
         const float fr = X - fl;
         const float tol = fmaf(tol1, X, tol0);
-        if (fr > tol && fr < 1.0f - tol) return (uint32_t)fl;
+        const bool sure = fr > tol && fr < 1.0f - tol;
+        uint32_t s = (uint32_t)fl;
+        if (__builtin_amdgcn_ballot_w64(!sure) != 0) {
+            const uint32_t s64 = (uint32_t)floor(expo64(w) / rate_dt);
+            if (!sure) s = s64;
+        }
+        return s;
     }
     return (uint32_t)floor(expo64(w) / rate_dt);
 }
@@ -282,27 +294,29 @@ __device__ __forceinline__ void flip_window(const PointConst &a, uint32_t path, 
 template <int DYN, int POT, bool KICK, typename R>
 __device__ __forceinline__ void pc_step(Path<R> &s, R h, R hh, R ngam, R dxi, R z, R A0, R A1)
 {
+    // The noise increment enters all three stages unchanged, so it is added to the
+    // noisy component once (vd / xd) instead of after each stage.
     if constexpr (DYN == DYN_INERTIAL) {
-        const R x = s.x, v = s.v;
+        const R x = s.x, v = s.v, vd = v + dxi;
         const R f1 = fma(ngam, v, force_plus<POT>(x, A0));
         const R xb = fma(v, h, x);
-        const R vb = fma(f1, h, v) + dxi;
+        const R vb = fma(f1, h, vd);
         const R f2 = fma(ngam, vb, force_plus<POT>(xb, A1));
         const R xp = fma(v + vb, hh, x);                       // predictor
-        const R vpr = fma(f1 + f2, hh, v) + dxi;
+        const R vpr = fma(f1 + f2, hh, vd);
         const R f3 = fma(ngam, vpr, force_plus<POT>(xp, A1));
         s.x = fma(v + vpr, hh, x);                             // corrector
-        R vn = fma(f1 + f3, hh, v) + dxi;
+        R vn = fma(f1 + f3, hh, vd);
         if constexpr (KICK) vn = vn + z;
         s.v = vn;
     } else {
-        const R x = s.x;
+        const R x = s.x, xd = x + dxi;
         const R f1 = force_plus<POT>(x, A0);
-        const R xb = fma(f1, h, x) + dxi;
+        const R xb = fma(f1, h, xd);
         const R f2 = force_plus<POT>(xb, A1);
-        const R xp = fma(f1 + f2, hh, x) + dxi;                // predictor
+        const R xp = fma(f1 + f2, hh, xd);                     // predictor
         const R f3 = force_plus<POT>(xp, A1);
-        R xn = fma(f1 + f3, hh, x) + dxi;                      // corrector
+        R xn = fma(f1 + f3, hh, xd);                           // corrector
         if constexpr (KICK) xn = xn + z;
         s.x = xn;
     }

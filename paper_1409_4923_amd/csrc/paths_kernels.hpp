@@ -134,7 +134,7 @@ __device__ __forceinline__ JGKick<R> jg_draw(const PointConst &a, uint32_t path,
     return e;
 }
 
-// Queue up to JG_CAP kicks of one window (wave-uniform loop, as for the fixed grid);
+// Queue up to jg_cap<R>() kicks of one window (wave-uniform loop, as for the fixed grid);
 // kicks beyond a full queue are drawn at their steps.
 template <typename R, int NOISE>
 __device__ __forceinline__ void jg_window(const PointConst &a, uint32_t path, uint32_t wlen, uint32_t &kP,
@@ -144,7 +144,7 @@ __device__ __forceinline__ void jg_window(const PointConst &a, uint32_t path, ui
     bool active = J.poff < wlen;
     while (__any(active)) {
         if (active) {
-            if (slot < JG_CAP) {
+            if (slot < jg_cap<R>()) {
                 q[slot * qs] = jg_draw<R, NOISE>(a, path, kP, J.poff, J.pth);
                 ++slot;
                 active = J.poff < wlen;
@@ -270,7 +270,7 @@ __device__ __forceinline__ void full_step(const PointConst &a, uint32_t path, Pa
 template <typename R, int NOISE> constexpr uint32_t queue_bytes()
 {
     return (queued_kicks<NOISE>() ? (JCAP + 1) * (uint32_t)sizeof(KickEntry<R>) : 0u) +
-           (((NOISE & NZ_JGRID) != 0) ? JG_CAP * (uint32_t)sizeof(JGKick<R>) : 0u) +
+           (((NOISE & NZ_JGRID) != 0) ? jg_cap<R>() * (uint32_t)sizeof(JGKick<R>) : 0u) +
            (((NOISE & NZ_DICH) != 0) ? (JCAP + 1) * 4u : 0u);
 }
 
@@ -293,7 +293,7 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
     JGKick<R> *gq = reinterpret_cast<JGKick<R> *>(smem);       // jump-adapted grid (no fixed-grid queue)
     uint32_t *fq = reinterpret_cast<uint32_t *>(
         smem + (queued_kicks<NOISE>() ? (JCAP + 1) * qs * sizeof(KickEntry<R>) : 0) +
-        (((NOISE & NZ_JGRID) != 0) ? JG_CAP * qs * sizeof(JGKick<R>) : 0));
+        (((NOISE & NZ_JGRID) != 0) ? jg_cap<R>() * qs * sizeof(JGKick<R>) : 0));
     JumpCursor<R> J[PPL];
     const R h = (R)a.dt, hh = (R)(0.5 * a.dt), ngam = (R)(-a.gamma), g3 = (R)a.g3;
     const R Fa = (R)a.Fa, Fb = (R)a.Fb;

@@ -55,7 +55,7 @@ size_t queue_lds_bytes(uint32_t noise, uint32_t prec, uint32_t ppl, uint32_t blo
     const size_t kick = prec == BM_F32 ? sizeof(KickEntry<float>) : sizeof(KickEntry<double>);
     size_t per = 0;
     const size_t jg = prec == BM_F32 ? sizeof(JGKick<float>) : sizeof(JGKick<double>);
-    if (noise & BM_NOISE_JUMP_GRID) per += JG_CAP * jg;
+    if (noise & BM_NOISE_JUMP_GRID) per += (prec == BM_F32 ? jg_cap<float>() : jg_cap<double>()) * jg;
     else if (noise & BM_NOISE_POISSON) per += (JCAP + 1) * kick;
     if (noise & BM_NOISE_DICH) per += (JCAP + 1) * 4;
     return per * ppl * block;
