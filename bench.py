@@ -503,6 +503,10 @@ def main():
         rec["cpu_baseline"]["single_core"] = {"value": one["value"], "sample": one["sample"]}
         rec["cpu_baseline"]["host_cpu"] = host_cpu_model()
         rec["speedup_vs_one_core"] = value / one["value"]
+        # the paper's figures (Sec. 6): GPU over the same program on one CPU core
+        rec["paper_speedup"] = {"fp32": 3000, "fp64": [700, 400],
+                                "hardware": "NVIDIA GeForce GTX TITAN Black vs one core of an "
+                                            "Intel Core i7-3930K at 3.2 GHz"}
     legs = [l for l in args.legs.split(",") if l and l != "none"]
     if "scan" in legs:
         rec["scan"] = scan_leg(args)
