@@ -25,14 +25,14 @@ namespace {
 // ---------------------------------------------------------------------------
 // Small layers
 // ---------------------------------------------------------------------------
-// Layer 1 (5 -> 256) + GELU; block = one row, lane = output; grid (rows, members).
-// Row r of member m reads x[idx ? idx[m * idx_stride + r] : row0 + r].
+// Layer 1 (5 -> 256) + GELU of the training forward; block = one row, lane = output;
+// grid (rows, members).  Row r of member m reads x[idx ? idx[m * idx_stride + r] : r].
 __global__ void __launch_bounds__(256) k_l1_fwd(const float *x, const uint32_t *idx, uint64_t idx_stride,
-                                                uint64_t row0, const bf16_t *wbf, const float *params,
-                                                int rows, float *u_out, float *z_out, bf16_t *a_out)
+                                                const bf16_t *wbf, const float *params, int rows, float *u_out,
+                                                float *z_out, bf16_t *a_out)
 {
     const int r = blockIdx.x, m = blockIdx.y, o = threadIdx.x;
-    const uint64_t src = idx ? (uint64_t)idx[(uint64_t)m * idx_stride + r] : row0 + (uint64_t)r;
+    const uint64_t src = idx ? (uint64_t)idx[(uint64_t)m * idx_stride + r] : (uint64_t)r;
     float u[IN];
     normalise(x + src * IN, u);
     const bf16_t *w = wbf + (uint64_t)m * NBF + BOFF_W1 + o * IN;
@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(256) k_l1_fwd(const float *x, const uint32_t *
 
 // Layer 4 (256 -> 1): one wave per row; grid (ceil(rows / 4), members).
 __global__ void __launch_bounds__(256) k_l4_fwd(const bf16_t *a3, const bf16_t *wbf, const float *params, int rows,
-                                                float *y, uint64_t y_stride, uint64_t y_off)
+                                                float *y)
 {
     const int m = blockIdx.y, lane = threadIdx.x & 63;
     const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(256) k_l4_fwd(const bf16_t *a3, const bf16_t *
     for (int i = 0; i < 4; ++i) s = fmaf(bf2f(a[lane * 4 + i]), bf2f(w[lane * 4 + i]), s);
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) y[(uint64_t)m * y_stride + y_off + r] = s + params[(uint64_t)m * NPARAM + OFF_B4];
+    if (lane == 0) y[(uint64_t)m * rows + r] = s + params[(uint64_t)m * NPARAM + OFF_B4];
 }
 
 // dy = 2 (y - t) / B and per-block sums of (y - t)^2; grid (ceil(B / 256), members).
@@ -305,14 +305,12 @@ size_t up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct MlpLayout {
     size_t u, z1, z2, z3, a1, a2, a3, y, dy, dz1, dz2, dz3, part, red, mean, stdv, blk, total;
-    uint64_t rows;    // rows per pass
 };
 
 MlpLayout mlp_layout(uint32_t nm, uint64_t batch, bool training)
 {
     MlpLayout L{};
     const uint64_t R = batch;
-    L.rows = R;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o += up(bytes); return at; };
     if (training) {                    // inference keeps its activations in registers
@@ -368,12 +366,11 @@ GemmArgs gemm_args()
     return g;
 }
 
-// Forward of `rows` rows through all members; y[m * y_stride + y_off + r].
 // ---------------------------------------------------------------------------
 // Fused inference: one work-group runs 128 rows of one member through all four
 // layers; activations never leave the registers.  The 256 x 256 layers are
 // computed transposed, Z^T = W A^T, with W as the MFMA A operand (staged through
-// LDS one 16-row tile at a time, double-buffered) and the activations as the B
+// LDS one 16-row tile at a time, triple-buffered) and the activations as the B
 // operand: a 16 x 16 output tile leaves lane (g = lane/16, c = lane%16) holding
 // features 4g..4g+3 of row c, which is exactly the B-operand slot of the next
 // layer if its contraction index is permuted -- k-step s, slot j of lane group g
@@ -513,17 +510,16 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *x, uint64_t rows
     }
 }
 
-hipError_t forward_pass(uint32_t nm, const float *params, const bf16_t *wbf, const float *x, const uint32_t *idx,
-                        uint64_t idx_stride, uint64_t row0, int rows, char *ws, const MlpLayout &L, bool training,
-                        float *y, uint64_t y_stride, uint64_t y_off, hipStream_t s)
+// Training forward of `rows` rows through all members, keeping what backward needs
+// (normalised inputs, pre-activations z, BF16 activations); y[m * rows + r].
+hipError_t train_forward(uint32_t nm, const float *params, const bf16_t *wbf, const float *x, const uint32_t *idx,
+                         uint64_t idx_stride, int rows, char *ws, const MlpLayout &L, float *y, hipStream_t s)
 {
     bf16_t *a1 = (bf16_t *)(ws + L.a1), *a2 = (bf16_t *)(ws + L.a2), *a3 = (bf16_t *)(ws + L.a3);
-    float *u = training ? (float *)(ws + L.u) : nullptr;
-    float *z1 = training ? (float *)(ws + L.z1) : nullptr;
-    float *z2 = training ? (float *)(ws + L.z2) : nullptr;
-    float *z3 = training ? (float *)(ws + L.z3) : nullptr;
-    hipLaunchKernelGGL(k_l1_fwd, dim3((uint32_t)rows, nm), dim3(256), 0, s, x, idx, idx_stride, row0, wbf, params,
-                       rows, u, z1, a1);
+    float *u = (float *)(ws + L.u), *z1 = (float *)(ws + L.z1);
+    float *z2 = (float *)(ws + L.z2), *z3 = (float *)(ws + L.z3);
+    hipLaunchKernelGGL(k_l1_fwd, dim3((uint32_t)rows, nm), dim3(256), 0, s, x, idx, idx_stride, wbf, params, rows,
+                       u, z1, a1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const bf16_t *ain[2] = {a1, a2};
@@ -541,8 +537,7 @@ hipError_t forward_pass(uint32_t nm, const float *params, const bf16_t *wbf, con
         e = gemm<EPI_FWD, false, false>(g, (int)nm, s);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_l4_fwd, dim3((uint32_t)((rows + 3) / 4), nm), dim3(256), 0, s, a3, wbf, params, rows, y,
-                       y_stride, y_off);
+    hipLaunchKernelGGL(k_l4_fwd, dim3((uint32_t)((rows + 3) / 4), nm), dim3(256), 0, s, a3, wbf, params, rows, y);
     return hipGetLastError();
 }
 
@@ -639,7 +634,7 @@ extern "C" int bm_mlp_backward(uint32_t n_members, const float *d_params, const 
     bf16_t *dz1 = (bf16_t *)(ws + L.dz1), *dz2 = (bf16_t *)(ws + L.dz2), *dz3 = (bf16_t *)(ws + L.dz3);
     float *part = (float *)(ws + L.part), *red = (float *)(ws + L.red);
 
-    hipError_t e = forward_pass(nm, d_params, wbf, d_x, d_idx, batch, 0, B, ws, L, true, y, batch, 0, s);
+    hipError_t e = train_forward(nm, d_params, wbf, d_x, d_idx, batch, B, ws, L, y, s);
     const int nblk = (B + 255) / 256;
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_loss, dim3(nblk, nm), dim3(256), 0, s, y, d_t, d_idx, batch, B, dy, part);
