@@ -377,7 +377,8 @@ GemmArgs gemm_args()
 // stands for feature 32 s + 4 g + j (j < 4) or 32 s + 16 + 4 g + (j - 4) (j >= 4),
 // and the W fragments are read from LDS in that order.
 // ---------------------------------------------------------------------------
-constexpr int FROWS = 128;             // rows per work-group: 4 waves x 2 tiles of 16
+constexpr int FROWS = 128;             // rows per work-group
+constexpr int INFER_RT = 2;            // row tiles of 16 per wave (4 waves per work-group)
 constexpr int FLDS = H + 8;            // padded row of a staged W tile (bf16)
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -389,9 +390,12 @@ __device__ __forceinline__ int perm_feature(int s, int g, int j)
     return 32 * s + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
 }
 
-__global__ void __launch_bounds__(256) k_mlp_infer(const float *x, uint64_t rows, const bf16_t *wbf,
-                                                   const float *params, float *y, uint64_t y_stride)
+// RT row tiles of 16 per wave; 128 / (16 RT) waves per work-group.
+template <int RT>
+__global__ void __launch_bounds__(64 * 8 / RT) k_mlp_infer(const float *x, uint64_t rows, const bf16_t *wbf,
+                                                           const float *params, float *y, uint64_t y_stride)
 {
+    constexpr int BT = 64 * 8 / RT;                      // threads per work-group
     __shared__ __align__(16) bf16_t sW[3][16 * FLDS];
     __shared__ __align__(16) float sL1[H * 8];          // per feature: W1[f][0..4], b1[f], pad
     __shared__ float sB[2][H], sW4[H];
@@ -399,37 +403,44 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *x, uint64_t rows
     const int m = blockIdx.y;
     const float *P = params + (uint64_t)m * NPARAM;
     const bf16_t *WB = wbf + (uint64_t)m * NBF;
+    if (t < H) {
 #pragma unroll
-    for (int j = 0; j < IN; ++j) sL1[t * 8 + j] = bf2f(WB[BOFF_W1 + t * IN + j]);
-    sL1[t * 8 + 5] = P[OFF_B1 + t];
-    sB[0][t] = P[OFF_B2 + t];
-    sB[1][t] = P[OFF_B3 + t];
-    sW4[t] = bf2f(WB[BOFF_W4 + t]);
+        for (int j = 0; j < IN; ++j) sL1[t * 8 + j] = bf2f(WB[BOFF_W1 + t * IN + j]);
+        sL1[t * 8 + 5] = P[OFF_B1 + t];
+        sB[0][t] = P[OFF_B2 + t];
+        sB[1][t] = P[OFF_B3 + t];
+        sW4[t] = bf2f(WB[BOFF_W4 + t]);
+    }
 
-    // staging of W tile ft (rows 16 ft .. 16 ft + 15, all 256 k): thread t moves 32 B
-    const int st_row = t >> 4, st_k = (t & 15) * 16;
-    auto load_tile = [&](const bf16_t *W, int ft, uint4 &v0, uint4 &v1) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(W + (uint64_t)(16 * ft + st_row) * H + st_k);
-        v0 = src[0];
-        v1 = src[1];
+    // staging of W tile ft (rows 16 ft .. 16 ft + 15, all 256 k) in 16-byte units:
+    // unit u = t + i BT is row u / 32, columns 8 (u % 32) .. + 7
+    constexpr int UNITS = 16 * H / 8 / BT;
+    auto load_tile = [&](const bf16_t *W, int ft, uint4 (&v)[UNITS]) {
+#pragma unroll
+        for (int i = 0; i < UNITS; ++i) {
+            const int u = t + i * BT;
+            v[i] = *reinterpret_cast<const uint4 *>(W + (uint64_t)(16 * ft + (u >> 5)) * H + (u & 31) * 8);
+        }
     };
-    auto store_tile = [&](int buf, const uint4 &v0, const uint4 &v1) {
-        uint4 *dst = reinterpret_cast<uint4 *>(&sW[buf][st_row * FLDS + st_k]);
-        dst[0] = v0;
-        dst[1] = v1;
+    auto store_tile = [&](int buf, const uint4 (&v)[UNITS]) {
+#pragma unroll
+        for (int i = 0; i < UNITS; ++i) {
+            const int u = t + i * BT;
+            *reinterpret_cast<uint4 *>(&sW[buf][(u >> 5) * FLDS + (u & 31) * 8]) = v[i];
+        }
     };
-    uint4 p0, p1;
-    load_tile(WB + BOFF_W2, 0, p0, p1);
-    store_tile(0, p0, p1);
-    load_tile(WB + BOFF_W2, 1, p0, p1);
-    store_tile(1, p0, p1);
+    uint4 pv[UNITS];
+    load_tile(WB + BOFF_W2, 0, pv);
+    store_tile(0, pv);
+    load_tile(WB + BOFF_W2, 1, pv);
+    store_tile(1, pv);
     __syncthreads();
 
     // ---- layer 1 (5 -> 256, FP32 FMA on the BF16 weights) into B operands ----
-    const uint64_t base = (uint64_t)blockIdx.x * FROWS + (uint64_t)wave * 32;
-    bf16x8 act[2][8];
+    const uint64_t base = (uint64_t)blockIdx.x * FROWS + (uint64_t)wave * 16 * RT;
+    bf16x8 act[RT][8];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
+    for (int rt = 0; rt < RT; ++rt) {
         const uint64_t r = base + 16 * rt + c;
         float u[IN];
         normalise(x + (r < rows ? r : 0) * IN, u);
@@ -454,9 +465,9 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *x, uint64_t rows
     // stored after its epilogue into the buffer tile T - 1 used, which every wave
     // finished reading before the barrier that ended iteration T - 2.  One barrier
     // per iteration also publishes tile T + 2 before iteration T + 1 reads it.
-    auto mma_tile = [&](int buf, floatx4 (&acc)[2]) {
-        acc[0] = floatx4{0.f, 0.f, 0.f, 0.f};
-        acc[1] = floatx4{0.f, 0.f, 0.f, 0.f};
+    auto mma_tile = [&](int buf, floatx4 (&acc)[RT]) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
         const bf16_t *wrow = &sW[buf][c * FLDS];
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
@@ -464,40 +475,40 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const float *x, uint64_t rows
             const bf16x4 hi = *reinterpret_cast<const bf16x4 *>(wrow + 32 * s + 16 + 4 * g);
             const bf16x8 a = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt)
+            for (int rt = 0; rt < RT; ++rt)
                 acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[rt][s], acc[rt], 0, 0, 0);
         }
     };
 #pragma unroll
     for (int layer = 0; layer < 2; ++layer) {
-        bf16x8 nxt[2][8];
-        floatx4 acc[2][2];
+        bf16x8 nxt[RT][8];
+        floatx4 acc[2][RT];
         mma_tile((16 * layer) % 3, acc[0]);
 #pragma unroll
         for (int ft = 0; ft < 16; ++ft) {
             const int T = 16 * layer + ft;
-            if (T + 2 < 32) load_tile(WB + ((T + 2) < 16 ? BOFF_W2 : BOFF_W3), (T + 2) & 15, p0, p1);
+            if (T + 2 < 32) load_tile(WB + ((T + 2) < 16 ? BOFF_W2 : BOFF_W3), (T + 2) & 15, pv);
             if (ft + 1 < 16) mma_tile((T + 1) % 3, acc[(ft + 1) & 1]);
             // epilogue of tile T: acc[rt][i] = Z^T[16 ft + 4 g + i][row c of tile rt]
             // -> next layer's slot (k-step ft / 2, j = 4 (ft % 2) + i)
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt)
+            for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                     nxt[rt][ft >> 1][4 * (ft & 1) + i] =
                         to_bf(gelu(acc[ft & 1][rt][i] + sB[layer][16 * ft + 4 * g + i]));
-            if (T + 2 < 32) store_tile((T + 2) % 3, p0, p1);
+            if (T + 2 < 32) store_tile((T + 2) % 3, pv);
             __syncthreads();
         }
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
+        for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int s = 0; s < 8; ++s) act[rt][s] = nxt[rt][s];
     }
 
     // ---- layer 4 (256 -> 1): partial dot per lane group, then across the 4 groups ----
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
+    for (int rt = 0; rt < RT; ++rt) {
         float sum = 0.0f;
 #pragma unroll
         for (int s = 0; s < 8; ++s)
@@ -602,8 +613,8 @@ extern "C" int bm_mlp_forward(uint32_t n_members, const float *d_params, const u
     rc = check_device(&dev);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_mlp_infer, dim3((uint32_t)((batch + FROWS - 1) / FROWS), n_members), dim3(256), 0, s, d_x,
-                       batch, (const bf16_t *)d_wbf, d_params, d_y, batch);
+    hipLaunchKernelGGL(k_mlp_infer<INFER_RT>, dim3((uint32_t)((batch + FROWS - 1) / FROWS), n_members),
+                       dim3(64 * 8 / INFER_RT), 0, s, d_x, batch, (const bf16_t *)d_wbf, d_params, d_y, batch);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? ok() : hip_fail(e, "bm_mlp_forward");
 }
@@ -723,8 +734,8 @@ extern "C" int bm_surrogate_query(uint32_t n_members, const float *d_params, con
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)d_ws;
     float *y = (float *)(ws + L.y);
-    hipLaunchKernelGGL(k_mlp_infer, dim3((uint32_t)((batch + FROWS - 1) / FROWS), n_members), dim3(256), 0, s, d_x,
-                       batch, (const bf16_t *)d_wbf, d_params, y, batch);
+    hipLaunchKernelGGL(k_mlp_infer<INFER_RT>, dim3((uint32_t)((batch + FROWS - 1) / FROWS), n_members),
+                       dim3(64 * 8 / INFER_RT), 0, s, d_x, batch, (const bf16_t *)d_wbf, d_params, y, batch);
     hipError_t e = hipGetLastError();
     const uint64_t nblk = (batch + 255) / 256;
     uint32_t *blk = (uint32_t *)(ws + L.blk);

@@ -174,7 +174,8 @@ def _ensemble_case(w, n_steps, n_window):
     _ensemble_case(W.C3, 100000, 10000),
     _ensemble_case(W.C1.with_(prec=W.F32, noise=W.NORMAL), 20000, 10000),
     _ensemble_case(W.C2.with_(noise=W.GAUSS | W.POISSON | W.JUMP_GRID), 40000, 20000),
-], ids=["c1-f32", "c2-f32", "c3-f32", "c1-normal-f32", "c2-jump-grid-f32"])
+    _ensemble_case(W.C3.with_(noise=W.NORMAL | W.DICH), 100000, 10000),
+], ids=["c1-f32", "c2-f32", "c3-f32", "c1-normal-f32", "c2-jump-grid-f32", "c3-normal-f32"])
 def test_fp32_mean_velocity_within_3se(w):
     say("FP32 <v> vs FP64 oracle: %s, %d paths x %d steps" % (w.name, w.n_paths, w.n_steps))
     e, ps = gpu_run(w, [w.n_steps])
