@@ -40,10 +40,10 @@ FP64_PEAK_FLOPS = 78.6e12
 # reads 0.5 GiB for it: factor 2.0; WRITE_SIZE reads 1 GiB: factor 1.0).  Valid
 # only while the integration kernel's sources hash to KERNEL_SOURCES_SHA256.
 TRAFFIC_WORKLOAD = "inertial-poisson-f32-2^20"
-TRAFFIC_BYTES_PER_LAUNCH = ((10987.5625 + 10498.0) / 2 * 2.0 + (28672.0 + 20480.0) / 2 * 1.0) * 1024
+TRAFFIC_BYTES_PER_LAUNCH = ((10992.4375 + 10498.0) / 2 * 2.0 + (28672.0 + 20480.0) / 2 * 1.0) * 1024
 KERNEL_SOURCES = ("common.hpp", "paths.hpp", "paths_kernels.hpp", "paths_tu.inc", "paths_f32_in.hip",
                   "launch.hpp")
-KERNEL_SOURCES_SHA256 = "c33c2ccd61b5083ff7c2ad23dd25248a7103e54e2b76587eefa883bad4cd057c"
+KERNEL_SOURCES_SHA256 = "eaf783e887ca7ad50bb79f5f1a911bf4420cc37d9283f6523e91fa3d3ab9e19d"
 
 
 def algorithmic_work(w):

@@ -268,6 +268,13 @@ PointConst point_const(const bm_model *m, const bm_run *r, const void *d_tab)
     // 1 - phi, v_log_f32 near 1, the scale); the tolerance is about 7x / 10x that.
     const double LN2 = 0.69314718055994530942;
     k.tol1 = 4e-6f;
+    // Jump window: the longest 16 2^j <= 1024 steps in which a lane expects at most
+    // about four jumps (the fastest rate of the model decides).
+    double rate_dt = 0.0;
+    if (m->noise & BM_NOISE_POISSON) rate_dt = std::fmax(rate_dt, m->shot_rate * h);
+    if (m->noise & BM_NOISE_DICH) rate_dt = std::fmax(rate_dt, std::fmax(m->dich_mua, m->dich_mub) * h);
+    k.jw_log2 = JW_LOG2_MAX;
+    while (k.jw_log2 > 4 && rate_dt * (double)(1u << k.jw_log2) > 4.5) --k.jw_log2;
     if (m->noise & BM_NOISE_POISSON) {
         k.lam_dt = m->shot_rate * h;
         k.zeta = m->shot_mean;

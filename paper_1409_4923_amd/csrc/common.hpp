@@ -96,13 +96,15 @@ struct Partial {
 // ---------------------------------------------------------------------------
 // Constants of one parameter point (one ensemble, or one point of a scan).
 // ---------------------------------------------------------------------------
+constexpr uint32_t JW_LOG2_MAX = 10;  // longest jump window of the path kernels: 1024 steps
+
 struct PointConst {
     const void *tab;      // forcing table, k < spp + 16 (float/double), see drive_at
     uint32_t spp;         // period of the forcing table in steps (1: no periodic drive)
     uint32_t point;       // point index in the random-stream counter
     uint32_t key0, key1;  // Philox key (seed)
     uint32_t n_paths;
-    uint32_t pad;
+    uint32_t jw_log2;     // jump window of 2^jw_log2 steps (>= 16)
     uint64_t n_steps;     // horizon (scan)
     uint64_t n_window;    // eq. (31): step index of t_i
     double dt, gamma;

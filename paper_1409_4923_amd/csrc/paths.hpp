@@ -126,13 +126,15 @@ template <int POT, typename R> __device__ __forceinline__ void fold(Path<R> &s)
 
 // ---------------------------------------------------------------------------
 // Jump processes on the dt grid.  The times and sizes of the jumps do not depend
-// on the path state, so each lane resolves all jumps of a window of JW steps in
+// on the path state, so each lane resolves all jumps of a window of steps in
 // one wave-uniform loop (the draws are the same as in Algorithms 3 / 4 step by
 // step) and queues them in LDS; the step loop then only compares the step
 // offset with the next queued offset.  A lane with more than JCAP jumps in a
-// window queues an "inline" marker and draws the rest at their steps.
+// window queues an "inline" marker and draws the rest at their steps.  The window
+// (16 2^k steps, at most 1024) is chosen per parameter point so that a lane
+// expects about four jumps in it: the wave-uniform loop runs as many iterations
+// as the lane with the most jumps, and the queue rarely overflows.
 // ---------------------------------------------------------------------------
-constexpr uint32_t JW = 256;          // jump window, a multiple of 16 steps
 constexpr uint32_t JCAP = 11;         // queued jumps per lane and window
 constexpr uint32_t INLINE_BIT = 0x80000000u;
 

@@ -276,7 +276,7 @@ template <typename R, int NOISE> constexpr uint32_t queue_bytes()
 
 // ---------------------------------------------------------------------------
 // The integration loop: advances PPL paths per lane over steps [n0, n1) in
-// windows of JW steps (aligned to multiples of JW).  Per window the jumps are
+// windows of 2^a.jw_log2 steps (aligned to multiples of it).  Per window the jumps are
 // queued, then the steps run in blocks of 16 sharing one Philox call for
 // Algorithm 2 (4 words x 4 base-6 digits; the normal increments of the
 // non-simplified scheme take one call per 4 steps) and 17 scalar loads of the
@@ -304,7 +304,8 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
     uint32_t k = (uint32_t)(n % a.spp);           // drive phase of step n
 
     while (n < n1) {
-        const uint64_t wend = ((n / JW) + 1u) * JW < n1 ? ((n / JW) + 1u) * JW : n1;
+        const uint64_t wnext = ((n >> a.jw_log2) + 1u) << a.jw_log2;
+        const uint64_t wend = wnext < n1 ? wnext : n1;
         const uint32_t wlen = (uint32_t)(wend - n);
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {

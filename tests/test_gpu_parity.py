@@ -95,13 +95,15 @@ def test_fp64_per_path_model_matrix(dyn, pot, noise):
 @pytest.mark.parametrize("dyn", [W.OVERDAMPED, W.INERTIAL])
 @pytest.mark.parametrize("noise", [W.POISSON, W.DICH, W.GAUSS | W.POISSON | W.DICH,
                                    W.POISSON | W.JUMP_GRID, W.GAUSS | W.POISSON | W.DICH | W.JUMP_GRID])
-def test_fp64_per_path_high_jump_rates(dyn, noise):
-    """Jump rates high enough that lanes exceed the per-window jump queue (lambda dt = 0.25,
-    flip probability ~0.2 per step), so later jumps are drawn at their steps."""
+@pytest.mark.parametrize("scale", [1.0, 4.0])
+def test_fp64_per_path_high_jump_rates(dyn, noise, scale):
+    """High jump rates (lambda dt = 0.25 or 1, flip probability ~0.2 or ~0.6 per step): the
+    jump window shrinks to 16 steps, and at the higher rates lanes exceed its queue, so
+    later jumps are drawn at their steps."""
     w = W.Workload(name="high-rate", dyn=dyn, pot=W.POT_SIN, noise=noise, prec=W.F64, n_paths=500,
-                   n_steps=1000, n_window=100, gamma=1.0, D=0.01, lam=25.0, zeta=0.02,
-                   Fa=0.5, Fb=0.5, mua=20.0, mub=25.0, dt=0.01, seed=5, x0_lo=0.0, x0_hi=1.0,
-                   v0_lo=-1.0, v0_hi=1.0)
+                   n_steps=1000, n_window=100, gamma=1.0, D=0.01, lam=25.0 * scale, zeta=0.02,
+                   Fa=0.5, Fb=0.5, mua=20.0 * scale, mub=25.0 * scale, dt=0.01, seed=5, x0_lo=0.0,
+                   x0_hi=1.0, v0_lo=-1.0, v0_hi=1.0)
     say("FP64 high jump rates dyn=%d noise=%d" % (dyn, noise))
     _, ps = gpu_run(w, [131, 869])
     xu, v, nz, _ = oracle_paths(w, 0, w.n_paths, 1000)
