@@ -165,6 +165,13 @@ template <typename R> struct KickEntry {
 // FP64 work sits behind a wave-uniform branch taken only when some lane needs it
 // (a few per cent of the draws); as a plain per-lane branch the compiler turns it
 // into a select and evaluates the FP64 log and divide for every draw.
+// The FP64 decision, out of line: inlined, its log and divide would be repeated at
+// every draw site of the unrolled step loop although they rarely run.
+__device__ __noinline__ uint32_t countdown_fp64(uint32_t w, double rate_dt)
+{
+    return (uint32_t)floor(expo64(w) / rate_dt);
+}
+
 template <typename R>
 __device__ __forceinline__ uint32_t countdown(uint32_t w, double rate_dt, float c, float tol0, float tol1)
 {
@@ -177,12 +184,12 @@ __device__ __forceinline__ uint32_t countdown(uint32_t w, double rate_dt, float 
         const bool sure = fr > tol && fr < 1.0f - tol;
         uint32_t s = (uint32_t)fl;
         if (__builtin_amdgcn_ballot_w64(!sure) != 0) {
-            const uint32_t s64 = (uint32_t)floor(expo64(w) / rate_dt);
+            const uint32_t s64 = countdown_fp64(w, rate_dt);
             if (!sure) s = s64;
         }
         return s;
     }
-    return (uint32_t)floor(expo64(w) / rate_dt);
+    return countdown_fp64(w, rate_dt);
 }
 
 // Kick amplitude z = zeta E (no decision depends on it: FP32 paths use v_log_f32).

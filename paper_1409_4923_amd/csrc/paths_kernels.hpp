@@ -112,6 +112,13 @@ __device__ __forceinline__ double piece_sqrt(double f) { return sqrt(f); }
 // exceeds it with probability below 10^-1000).
 constexpr uint32_t JG_MAX_KICKS = 4096;
 
+// Time of the next kick in steps from the start of the current one's step: th + E /
+// (lambda dt) in FP64 (out of line: it is needed once per kick, not per step).
+__device__ __noinline__ double jg_next_time(double th, uint32_t w, double lam_dt)
+{
+    return th + expo64(w) / lam_dt;
+}
+
 // Draws the kick that falls at (off, th) of the window -- its amplitude, the
 // increment of the piece after it -- and the time of the next kick, counted from
 // it in FP64: off += floor(T), th = T - floor(T) with T = th + E / (lambda dt).
@@ -126,7 +133,7 @@ __device__ __forceinline__ JGKick<R> jg_draw(const PointConst &a, uint32_t path,
     e.th = (R)th;
     e.z = amplitude<R>(a, second ? b.w : b.y);
     e.u = piece_noise<R, NOISE>(a, path, kP, (R)a.g3);
-    const double T = th + expo64(second ? b.z : b.x) / a.lam_dt;
+    const double T = jg_next_time(th, second ? b.z : b.x, a.lam_dt);
     const double Tf = floor(T);
     off += (uint32_t)Tf;                     // < 2^31 + window: validated on the host
     th = T - Tf;
@@ -170,10 +177,11 @@ __device__ __forceinline__ void jg_advance(const PointConst &a, uint32_t path, u
     else J.g.off = JG_NONE;
 }
 
-// One step of the jump-adapted grid.  Every lane integrates the first piece of its
-// step -- the whole step, or up to its first kick at t_n + theta dt -- with the
-// same instructions; lanes with a kick then integrate the remaining pieces (one
-// per further kick in the step, then the rest of the step).  The first piece
+// One step of the jump-adapted grid.  When no lane of the wave has a kick in this
+// step it is a plain Algorithm 1 step.  Otherwise every lane integrates the first
+// piece of its step -- the whole step, or up to its first kick at t_n + theta dt --
+// with the same instructions; lanes with a kick then integrate the remaining pieces
+// (one per further kick in the step, then the rest of the step).  The first piece
 // takes the step's own Gaussian increment scaled by sqrt(theta); a piece after
 // kick k takes the increment drawn for k.
 template <typename R, int DYN, int POT, int NOISE>
@@ -182,6 +190,10 @@ __device__ __forceinline__ void jg_step(const PointConst &a, uint32_t path, Path
                                         uint32_t kph, R dxi, R h, R hh, R ngam, R A0, R A1, R lev)
 {
     const bool kick = J.g.off == off;
+    if (__builtin_amdgcn_ballot_w64(kick) == 0) {           // no lane of the wave kicks now
+        pc_step<DYN, POT, false, R>(s, h, hh, ngam, dxi, R(0), A0, A1);
+        return;
+    }
     R th1 = R(1), A_e = A1, dxi1 = dxi, z1 = R(0);
     if (kick) {
         th1 = J.g.th;
