@@ -213,7 +213,7 @@ def scheme_leg(args):
     stream = torch.cuda.current_stream(dev)
     out = torch.empty(B.STATS_BYTES, dtype=torch.uint8, device=dev)
 
-    def run(w, reps=2):
+    def run(w, reps=5):
         m, r = W.to_c(w)
         nb = B.bm_ensemble_workspace_size(m, r)
         ws = torch.empty(nb, dtype=torch.uint8, device=dev)
@@ -241,6 +241,7 @@ def scheme_leg(args):
         res[name] = {"three_point": a, "normal": b, "speedup": a["path_steps_per_s"] / b["path_steps_per_s"]}
     ref = run(base.with_(prec=W.F32, noise=W.NORMAL, spp=4 * base.spp, n_steps=4 * base.n_steps,
                          n_window=4 * base.n_window), reps=1)
+    # best of five launches per variant: each lasts only some 20 ms
     res["reference_quarter_dt"] = {"mean_v": ref["mean_v"], "se_v": ref["se_v"]}
     for k in ("three_point", "normal"):
         d = res["f32"][k]["mean_v"] - ref["mean_v"]
