@@ -129,11 +129,12 @@ template <int POT, typename R> __device__ __forceinline__ void fold(Path<R> &s)
 // on the path state, so each lane resolves all jumps of a window of steps in
 // one wave-uniform loop (the draws are the same as in Algorithms 3 / 4 step by
 // step) and queues them in LDS; the step loop then only compares the step
-// offset with the next queued offset.  A lane with more than JCAP jumps in a
-// window queues an "inline" marker and draws the rest at their steps.  The window
-// (16 2^k steps, at most 1024) is chosen per parameter point so that a lane
-// expects about four jumps in it: the wave-uniform loop runs as many iterations
-// as the lane with the most jumps, and the queue rarely overflows.
+// offset with the next queued offset.  The window (16 2^k steps, at most 1024) is
+// chosen per parameter point so that a lane expects about four jumps in it: the
+// wave-uniform loop runs as many iterations as the lane with the most jumps, and
+// a queue rarely fills up.  A full kick queue ends the window early for the whole
+// wave (at the first kick it does not hold); a lane with more than JCAP flips in a
+// window queues an "inline" marker and draws the rest at their steps.
 // ---------------------------------------------------------------------------
 constexpr uint32_t JCAP = 11;         // queued jumps per lane and window
 constexpr uint32_t INLINE_BIT = 0x80000000u;
@@ -152,8 +153,8 @@ constexpr uint32_t JG_NONE = 0xFFFFFFFFu;
 template <typename R> constexpr uint32_t jg_cap() { return sizeof(R) == 4 ? 10u : 6u; }
 
 template <typename R> struct KickEntry {
-    uint32_t off;   // step offset in the window (>= window length: none left)
-    R z;            // amplitude; < 0 marks "draw inline from here"
+    uint32_t off;   // step offset in the window (>= the steps run: none left)
+    R z;            // amplitude
 };
 
 // Exponential countdown s = floor(E / (rate dt)), E = -ln(1 - phi), phi = w 2^-32,
@@ -212,14 +213,6 @@ __device__ __forceinline__ void kick_from(const PointConst &a, uint32_t ws, uint
     z = amplitude<R>(a, wz);
 }
 
-template <typename R>
-__device__ __forceinline__ void kick_draw(const PointConst &a, uint32_t path, uint32_t k, uint32_t &s, R &z)
-{
-    const U4 q = philox4x32_10(k >> 1, path, a.point, TAG_POISSON, a.key0, a.key1);
-    const bool second = (k & 1u) != 0u;
-    kick_from<R>(a, second ? q.z : q.x, second ? q.w : q.y, s, z);
-}
-
 // Algorithm 4 draw for flip number m into state d_new: dwell s (steps).
 template <typename R>
 __device__ __forceinline__ uint32_t flip_draw(const PointConst &a, uint32_t path, uint32_t m, int32_t d_new)
@@ -233,9 +226,11 @@ __device__ __forceinline__ uint32_t flip_draw(const PointConst &a, uint32_t path
 // Queue the kicks of one window.  `off` is the offset of the next kick (the
 // Algorithm 3 countdown at the window start).  q[slot * qs] is this lane's queue.
 // One Philox block holds two kicks: an iteration uses both halves when it can.
+// Returns the number of leading steps of the window whose kicks are all queued:
+// wlen, or, when the queue is full, the offset of the first kick it does not hold.
 template <typename R>
-__device__ __forceinline__ void kick_window(const PointConst &a, uint32_t path, uint32_t wlen, uint32_t off,
-                                            uint32_t &kP, KickEntry<R> *q, uint32_t qs)
+__device__ __forceinline__ uint32_t kick_window(const PointConst &a, uint32_t path, uint32_t wlen, uint32_t off,
+                                                uint32_t &kP, KickEntry<R> *q, uint32_t qs)
 {
     uint32_t slot = 0;
     bool active = off < wlen;
@@ -261,11 +256,27 @@ __device__ __forceinline__ void kick_window(const PointConst &a, uint32_t path, 
                     active = off < wlen;
                 }
             } else {
-                active = false;      // queue full: the rest of the window is drawn inline
+                active = false;      // queue full: the window ends at this kick
             }
         }
     }
-    q[slot * qs] = KickEntry<R>{off, (slot == JCAP && off < wlen) ? R(-1) : R(0)};
+    q[slot * qs] = KickEntry<R>{off, R(0)};
+    return off < wlen ? off : wlen;
+}
+
+// Jumps queued in slots below JCAP at offsets in [from, wlen): drawn for a window
+// of wlen steps that ended after `from` steps.  Offsets rise along the queue and
+// the entry after the last queued jump lies at or beyond wlen (or at slot JCAP).
+template <typename T, typename OffOf>
+__device__ __forceinline__ uint32_t queued_beyond(const T *q, uint32_t qs, uint32_t from, uint32_t wlen, OffOf off_of)
+{
+    uint32_t c = 0;
+    for (uint32_t slot = 0; slot < JCAP; ++slot) {
+        const uint32_t o = off_of(q[slot * qs]);
+        if (o >= wlen) break;
+        c += (o >= from) ? 1u : 0u;
+    }
+    return c;
 }
 
 // Queue the flips of one window; bit INLINE_BIT marks "draw inline from here".

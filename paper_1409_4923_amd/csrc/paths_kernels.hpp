@@ -55,8 +55,8 @@ template <typename R> __device__ __forceinline__ R drive_at(const PointConst &a,
 
 template <typename R> struct JumpCursor {
     uint32_t nP;    // offset of the next kick in the window
-    R zP;           // its amplitude (< 0: kicks are drawn inline from nP on)
-    uint32_t cP;    // element index of the next queue slot (slot * qs)
+    R zP;           // its amplitude
+    const KickEntry<R> *pP;   // the queue entry after it
     uint32_t nD;    // offset of the next flip
     uint32_t cD;    // element index of the next queue slot (FLIP_INLINE: drawn inline)
     // jump-adapted grid
@@ -222,33 +222,17 @@ __device__ __forceinline__ void jg_step(const PointConst &a, uint32_t path, Path
     }
 }
 
-// One step of one path at window offset `off` (drive phase kph): jumps due at this
-// step, then Algorithm 1.  `dxi` is the Algorithm 2 increment.  (Folding is done
-// by the caller.)
+// One step of one path at window offset `off` (drive phase kph): flips due at this
+// step, Algorithm 1, and the Poisson kick due at this step, which Algorithm 3 adds
+// to the corrector's result.  `dxi` is the Algorithm 2 increment.  (Folding is
+// done by the caller.)
 template <typename R, int DYN, int POT, int NOISE>
 __device__ __forceinline__ void full_step(const PointConst &a, uint32_t path, Path<R> &s, JumpCursor<R> &J,
-                                          const KickEntry<R> *kq, const JGKick<R> *gq, const uint32_t *fq,
+                                          const JGKick<R> *gq, const uint32_t *fq,
                                           uint32_t qs, uint32_t wlen, uint32_t off, uint32_t kph, R dxi, R h,
                                           R hh, R ngam,
                                           R A0, R A1, R Fa, R Fb)
 {
-    R z = R(0);
-    if constexpr (queued_kicks<NOISE>()) {
-        if (J.nP == off) {                       // Algorithm 3: s <= 0 at this step
-            if (J.zP >= R(0)) {
-                z = J.zP;
-                const KickEntry<R> e = kq[J.cP];
-                J.cP += qs;
-                J.nP = e.off;
-                J.zP = e.z;
-            } else {
-                uint32_t sn;
-                kick_draw<R>(a, path, s.kP, sn, z);
-                ++s.kP;
-                J.nP = off + 1u + sn;
-            }
-        }
-    }
     if constexpr ((NOISE & NZ_DICH) != 0) {
         if (J.nD == off) {                       // Algorithm 4: s <= 0 at this step
             s.d = 1 - s.d;
@@ -273,7 +257,17 @@ __device__ __forceinline__ void full_step(const PointConst &a, uint32_t path, Pa
     if constexpr ((NOISE & NZ_JGRID) != 0) {
         jg_step<R, DYN, POT, NOISE>(a, path, s, J, gq, qs, wlen, off, kph, dxi, h, hh, ngam, A0, A1, lev);
     } else {
-        pc_step<DYN, POT, (NOISE & NZ_POISSON) != 0, R>(s, h, hh, ngam, dxi, z, A0, A1);
+        pc_step<DYN, POT, false, R>(s, h, hh, ngam, dxi, R(0), A0, A1);
+    }
+    if constexpr (queued_kicks<NOISE>()) {
+        if (J.nP == off) {                       // Algorithm 3: s <= 0 at this step
+            if constexpr (DYN == DYN_INERTIAL) s.v = s.v + J.zP;
+            else s.x = s.x + J.zP;
+            const KickEntry<R> e = *J.pP;
+            J.pP += qs;
+            J.nP = e.off;
+            J.zP = e.z;
+        }
     }
 }
 
@@ -317,8 +311,10 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
 
     while (n < n1) {
         const uint64_t wnext = ((n >> a.jw_log2) + 1u) << a.jw_log2;
-        const uint64_t wend = wnext < n1 ? wnext : n1;
-        const uint32_t wlen = (uint32_t)(wend - n);
+        uint64_t wend = wnext < n1 ? wnext : n1;
+        const uint32_t wdrawn = (uint32_t)(wend - n);   // steps the queues were drawn for
+        uint32_t wlen = wdrawn;
+        uint32_t cover = wdrawn;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
             if constexpr ((NOISE & NZ_JGRID) != 0) {
@@ -327,17 +323,35 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                 jg_window<R, NOISE>(a, path[j], wlen, s[j].kP, J[j], gq + col(j), qs);
             }
             if constexpr (queued_kicks<NOISE>()) {
-                kick_window<R>(a, path[j], wlen, (uint32_t)s[j].sP, s[j].kP, kq + col(j), qs);
+                const uint32_t c = kick_window<R>(a, path[j], wlen, (uint32_t)s[j].sP, s[j].kP, kq + col(j), qs);
+                cover = c < cover ? c : cover;
                 const KickEntry<R> e = kq[col(j)];
                 J[j].nP = e.off;
                 J[j].zP = e.z;
-                J[j].cP = qs;                       // element index of slot 1
+                J[j].pP = kq + col(j) + qs;
             }
             if constexpr ((NOISE & NZ_DICH) != 0) {
                 flip_window<R>(a, path[j], wlen, (uint32_t)s[j].sD, s[j].mD, s[j].d, fq + col(j), qs);
                 const uint32_t e = fq[col(j)];
                 J[j].nD = e & ~INLINE_BIT;
                 J[j].cD = (e & INLINE_BIT) ? FLIP_INLINE : qs;
+            }
+        }
+        if constexpr (queued_kicks<NOISE>()) {
+            // A full kick queue ends the window for the wave at the first kick it
+            // does not hold (the minimum over the lanes, at least JCAP steps in),
+            // rounded down to a 16-step block boundary when one lies after n.
+            if (__any(cover < wlen)) {
+                uint32_t wl = wlen;
+                for (;;) {
+                    const uint64_t b = __ballot(cover < wl);
+                    if (b == 0) break;
+                    wl = (uint32_t)__shfl(cover, __ffsll((long long)b) - 1);
+                }
+                uint64_t we = n + wl;
+                if ((we & ~(uint64_t)15) > n) we &= ~(uint64_t)15;
+                wend = we;
+                wlen = (uint32_t)(we - n);
             }
         }
         uint32_t off = 0;
@@ -365,7 +379,7 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                     normal_pair(hi ? q.z : q.x, hi ? q.w : q.y, zc, zs);
                     dxi = g3 * ((n & 1u) ? zs : zc);
                 }
-                full_step<R, DYN, POT, NOISE>(a, path[j], s[j], J[j], kq + col(j), gq + col(j), fq + col(j), qs,
+                full_step<R, DYN, POT, NOISE>(a, path[j], s[j], J[j], gq + col(j), fq + col(j), qs,
                                               wlen, off, k,
                                               dxi, h, hh, ngam, A0, A1, Fa, Fb);
             }
@@ -418,7 +432,7 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                             u[j] = times6(u[j]);   // next base-6 digit
                         }
                         if constexpr ((NOISE & NZ_NORMAL) != 0) dxi = g3 * zn[j][dg];
-                        full_step<R, DYN, POT, NOISE>(a, path[j], s[j], J[j], kq + col(j), gq + col(j),
+                        full_step<R, DYN, POT, NOISE>(a, path[j], s[j], J[j], gq + col(j),
                                                       fq + col(j), qs, wlen, off, k + (uint32_t)(4 * wd + dg), dxi, h, hh, ngam,
                                                       A0, A1, Fa, Fb);
                     }
@@ -433,15 +447,26 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
 
         while (n < wend) one_step();
 
-        // Countdowns at the window end: the next jump lies at or beyond it.
+        // Countdowns at the window end: the next jump lies at or beyond it.  A window
+        // that ended early gives back the draws of the jumps queued past its end.
+        const bool early = wlen < wdrawn;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-            if constexpr (queued_kicks<NOISE>()) s[j].sP = (int32_t)(J[j].nP - wlen);
+            if constexpr (queued_kicks<NOISE>()) {
+                s[j].sP = (int32_t)(J[j].nP - wlen);
+                if (early)
+                    s[j].kP -= queued_beyond(kq + col(j), qs, wlen, wdrawn,
+                                             [](const KickEntry<R> &e) { return e.off; });
+            }
             if constexpr ((NOISE & NZ_JGRID) != 0) {
                 s[j].sP = (int32_t)(J[j].poff - wlen);
                 s[j].thP = J[j].pth;
             }
-            if constexpr ((NOISE & NZ_DICH) != 0) s[j].sD = (int32_t)(J[j].nD - wlen);
+            if constexpr ((NOISE & NZ_DICH) != 0) {
+                s[j].sD = (int32_t)(J[j].nD - wlen);
+                if (queued_kicks<NOISE>() && early)
+                    s[j].mD -= queued_beyond(fq + col(j), qs, wlen, wdrawn, [](uint32_t e) { return e; });
+            }
         }
     }
 }

@@ -240,7 +240,15 @@ def test_chunking_invariance(prec):
 
 @pytest.mark.parametrize("ppl,block", [(1, 64), (1, 512), (2, 128), (2, 256)])
 def test_launch_shape_invariance(ppl, block):
-    for w in (W.C2.with_(n_paths=5003), W.C3.with_(n_paths=5003)):
+    # busy jumps (lambda dt = 0.5): kick queues fill up, so windows end early at
+    # wave-dependent steps and give back the kicks and flips queued past their end
+    # (with flips the queues of 512 lanes exceed the LDS limit)
+    busy = W.C2.with_(name="busy-jumps", n_paths=5003, noise=W.GAUSS | W.POISSON, lam=156.0)
+    ws = [W.C2.with_(n_paths=5003), W.C3.with_(n_paths=5003), busy]
+    if ppl * block <= 256:
+        ws.append(busy.with_(name="busy-jumps-flips", noise=W.GAUSS | W.POISSON | W.DICH, Fa=0.5, Fb=0.5,
+                             mua=60.0, mub=80.0))
+    for w in ws:
         _, a = gpu_run(w, [700])
         _, b = gpu_run(w, [700], tune=B.make_tune(ppl, block))
         for f in ("x", "v", "noise"):
