@@ -39,16 +39,34 @@ template <typename R> struct Path {
 // tilt, Poisson bias, dichotomous level) plus the potential's constant offset
 // pot_offset<POT>() (folded into the drive table on the host).
 // ---------------------------------------------------------------------------
-template <int POT> __device__ __forceinline__ float force_plus(float x, float A)
+// The potential's constant factor of the force: -2 pi (sine) or 2 pi (ratchet).
+// In FP32 it is held in a vector register the compiler cannot see through: the
+// forcing A is wave-uniform and lives in a scalar register, an FMA may read only
+// one scalar operand, and with the factor as a literal (a second one) the compiler
+// would copy A into a vector register at every use.  Formed once per kernel.
+template <int POT, typename R> __device__ __forceinline__ R pot_factor()
 {
-    constexpr float TWO_PI = 6.28318530717958648f;
+    constexpr double TWO_PI = 6.28318530717958647692;
+    const R c = (R)(POT == POT_SIN ? -TWO_PI : TWO_PI);
+    if constexpr (sizeof(R) == 4) {
+        R r;
+        asm volatile("; pot_factor" : "=v"(r) : "0"(c));
+        return r;
+    } else {
+        return c;
+    }
+}
+
+// -V'(x) + A, with kp = pot_factor<POT>().
+template <int POT> __device__ __forceinline__ float force_plus(float x, float A, float kp)
+{
     if constexpr (POT == POT_SIN) {
         // V = sin(2 pi x): -V' = -2 pi cos(2 pi x); v_cos_f32 takes its argument in turns
-        return __builtin_fmaf(-TWO_PI, __builtin_amdgcn_cosf(x), A);
+        return __builtin_fmaf(kp, __builtin_amdgcn_cosf(x), A);
     } else if constexpr (POT == POT_RATCHET) {
         // V = -sin 2 pi x - sin(4 pi x)/4:  -V' = 2 pi c + pi (2 c^2 - 1) = c (2 pi c + 2 pi) - pi
         const float c = __builtin_amdgcn_cosf(x);
-        return __builtin_fmaf(c, __builtin_fmaf(TWO_PI, c, TWO_PI), A);   // A includes -pi
+        return __builtin_fmaf(c, __builtin_fmaf(kp, c, kp), A);           // A includes -pi
     } else if constexpr (POT == POT_TENT) {
         // eq. (2), period 2: +1 on [0, 1] (V = 1 - x), -1 on (1, 2) (V = 1 + x shifted)
         const float y = x - 2.0f * floorf(x * 0.5f);
@@ -58,14 +76,14 @@ template <int POT> __device__ __forceinline__ float force_plus(float x, float A)
     }
 }
 
-template <int POT> __device__ __forceinline__ double force_plus(double x, double A)
+template <int POT> __device__ __forceinline__ double force_plus(double x, double A, double kp)
 {
     constexpr double PI = 3.14159265358979323846;
     if constexpr (POT == POT_SIN) {
-        return fma(-2.0 * PI, cos(2.0 * PI * x), A);
+        return fma(kp, cos(2.0 * PI * x), A);
     } else if constexpr (POT == POT_RATCHET) {
         const double c = cos(2.0 * PI * x);
-        return fma(c, fma(2.0 * PI, c, 2.0 * PI), A);                     // A includes -pi
+        return fma(c, fma(kp, c, kp), A);                                 // A includes -pi
     } else if constexpr (POT == POT_TENT) {
         const double y = x - 2.0 * floor(x / 2.0);
         return (y <= 1.0 ? 1.0 : -1.0) + A;
@@ -312,30 +330,30 @@ __device__ __forceinline__ void flip_window(const PointConst &a, uint32_t path, 
 // cosines, twelve FMAs and seven adds (inertial).
 // ---------------------------------------------------------------------------
 template <int DYN, int POT, bool KICK, typename R>
-__device__ __forceinline__ void pc_step(Path<R> &s, R h, R hh, R ngam, R dxi, R z, R A0, R A1)
+__device__ __forceinline__ void pc_step(Path<R> &s, R h, R hh, R ngam, R kp, R dxi, R z, R A0, R A1)
 {
     // The noise increment enters all three stages unchanged, so it is added to the
     // noisy component once (vd / xd) instead of after each stage.
     if constexpr (DYN == DYN_INERTIAL) {
         const R x = s.x, v = s.v, vd = v + dxi;
-        const R f1 = fma(ngam, v, force_plus<POT>(x, A0));
+        const R f1 = fma(ngam, v, force_plus<POT>(x, A0, kp));
         const R xb = fma(v, h, x);
         const R vb = fma(f1, h, vd);
-        const R f2 = fma(ngam, vb, force_plus<POT>(xb, A1));
+        const R f2 = fma(ngam, vb, force_plus<POT>(xb, A1, kp));
         const R xp = fma(v + vb, hh, x);                       // predictor
         const R vpr = fma(f1 + f2, hh, vd);
-        const R f3 = fma(ngam, vpr, force_plus<POT>(xp, A1));
+        const R f3 = fma(ngam, vpr, force_plus<POT>(xp, A1, kp));
         s.x = fma(v + vpr, hh, x);                             // corrector
         R vn = fma(f1 + f3, hh, vd);
         if constexpr (KICK) vn = vn + z;
         s.v = vn;
     } else {
         const R x = s.x, xd = x + dxi;
-        const R f1 = force_plus<POT>(x, A0);
+        const R f1 = force_plus<POT>(x, A0, kp);
         const R xb = fma(f1, h, xd);
-        const R f2 = force_plus<POT>(xb, A1);
+        const R f2 = force_plus<POT>(xb, A1, kp);
         const R xp = fma(f1 + f2, hh, xd);                     // predictor
-        const R f3 = force_plus<POT>(xp, A1);
+        const R f3 = force_plus<POT>(xp, A1, kp);
         R xn = fma(f1 + f3, hh, xd);                           // corrector
         if constexpr (KICK) xn = xn + z;
         s.x = xn;

@@ -187,11 +187,11 @@ __device__ __forceinline__ void jg_advance(const PointConst &a, uint32_t path, u
 template <typename R, int DYN, int POT, int NOISE>
 __device__ __forceinline__ void jg_step(const PointConst &a, uint32_t path, Path<R> &s, JumpCursor<R> &J,
                                         const JGKick<R> *q, uint32_t qs, uint32_t wlen, uint32_t off,
-                                        uint32_t kph, R dxi, R h, R hh, R ngam, R A0, R A1, R lev)
+                                        uint32_t kph, R dxi, R h, R hh, R ngam, R kp, R A0, R A1, R lev)
 {
     const bool kick = J.g.off == off;
     if (__builtin_amdgcn_ballot_w64(kick) == 0) {           // no lane of the wave kicks now
-        pc_step<DYN, POT, false, R>(s, h, hh, ngam, dxi, R(0), A0, A1);
+        pc_step<DYN, POT, false, R>(s, h, hh, ngam, kp, dxi, R(0), A0, A1);
         return;
     }
     R th1 = R(1), A_e = A1, dxi1 = dxi, z1 = R(0);
@@ -201,7 +201,7 @@ __device__ __forceinline__ void jg_step(const PointConst &a, uint32_t path, Path
         dxi1 = dxi * piece_sqrt(th1);
         z1 = J.g.z;
     }
-    pc_step<DYN, POT, true, R>(s, th1 * h, th1 * hh, ngam, dxi1, z1, A0, A_e);
+    pc_step<DYN, POT, true, R>(s, th1 * h, th1 * hh, ngam, kp, dxi1, z1, A0, A_e);
     if (kick) {
         R from = th1, A_from = A_e, u = J.g.u;
         jg_advance<R, NOISE>(a, path, wlen, s.kP, J, q, qs);
@@ -210,14 +210,14 @@ __device__ __forceinline__ void jg_step(const PointConst &a, uint32_t path, Path
         for (uint32_t it = 0; J.g.off == off && it < JG_MAX_KICKS; ++it) {
             const R th = J.g.th;
             const R A_th = drive_inside<R>(a, kph, (double)th) + lev;
-            pc_step<DYN, POT, true, R>(s, (th - from) * h, (th - from) * hh, ngam, u * piece_sqrt(th - from), J.g.z,
+            pc_step<DYN, POT, true, R>(s, (th - from) * h, (th - from) * hh, ngam, kp, u * piece_sqrt(th - from), J.g.z,
                                        A_from, A_th);
             from = th;
             A_from = A_th;
             u = J.g.u;
             jg_advance<R, NOISE>(a, path, wlen, s.kP, J, q, qs);
         }
-        pc_step<DYN, POT, false, R>(s, (R(1) - from) * h, (R(1) - from) * hh, ngam, u * piece_sqrt(R(1) - from),
+        pc_step<DYN, POT, false, R>(s, (R(1) - from) * h, (R(1) - from) * hh, ngam, kp, u * piece_sqrt(R(1) - from),
                                     R(0), A_from, A1);
     }
 }
@@ -230,7 +230,7 @@ template <typename R, int DYN, int POT, int NOISE>
 __device__ __forceinline__ void full_step(const PointConst &a, uint32_t path, Path<R> &s, JumpCursor<R> &J,
                                           const JGKick<R> *gq, const uint32_t *fq,
                                           uint32_t qs, uint32_t wlen, uint32_t off, uint32_t kph, R dxi, R h,
-                                          R hh, R ngam,
+                                          R hh, R ngam, R kp,
                                           R A0, R A1, R Fa, R Fb)
 {
     if constexpr ((NOISE & NZ_DICH) != 0) {
@@ -255,9 +255,9 @@ __device__ __forceinline__ void full_step(const PointConst &a, uint32_t path, Pa
         A1 = A1 + lev;
     }
     if constexpr ((NOISE & NZ_JGRID) != 0) {
-        jg_step<R, DYN, POT, NOISE>(a, path, s, J, gq, qs, wlen, off, kph, dxi, h, hh, ngam, A0, A1, lev);
+        jg_step<R, DYN, POT, NOISE>(a, path, s, J, gq, qs, wlen, off, kph, dxi, h, hh, ngam, kp, A0, A1, lev);
     } else {
-        pc_step<DYN, POT, false, R>(s, h, hh, ngam, dxi, R(0), A0, A1);
+        pc_step<DYN, POT, false, R>(s, h, hh, ngam, kp, dxi, R(0), A0, A1);
     }
     if constexpr (queued_kicks<NOISE>()) {
         if (J.nP == off) {                       // Algorithm 3: s <= 0 at this step
@@ -302,6 +302,7 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
         (((NOISE & NZ_JGRID) != 0) ? jg_cap<R>() * qs * sizeof(JGKick<R>) : 0));
     JumpCursor<R> J[PPL];
     const R h = (R)a.dt, hh = (R)(0.5 * a.dt), ngam = (R)(-a.gamma), g3 = (R)a.g3;
+    const R kp = pot_factor<POT, R>();
     const R Fa = (R)a.Fa, Fb = (R)a.Fb;
     const uint32_t wave_cols = qs / PPL;
     auto col = [&](int j) { return (uint32_t)j * wave_cols + col0; };
@@ -346,7 +347,9 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                 for (;;) {
                     const uint64_t b = __ballot(cover < wl);
                     if (b == 0) break;
-                    wl = (uint32_t)__shfl(cover, __ffsll((long long)b) - 1);
+                    // one lane's value, the same in every lane: keep it scalar, so
+                    // that step counters and forcing-table reads stay wave-uniform
+                    wl = __builtin_amdgcn_readfirstlane((uint32_t)__shfl(cover, __ffsll((long long)b) - 1));
                 }
                 uint64_t we = n + wl;
                 if ((we & ~(uint64_t)15) > n) we &= ~(uint64_t)15;
@@ -381,7 +384,7 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                 }
                 full_step<R, DYN, POT, NOISE>(a, path[j], s[j], J[j], gq + col(j), fq + col(j), qs,
                                               wlen, off, k,
-                                              dxi, h, hh, ngam, A0, A1, Fa, Fb);
+                                              dxi, h, hh, ngam, kp, A0, A1, Fa, Fb);
             }
             k = (k + 1u == a.spp) ? 0u : k + 1u;
             ++n;
@@ -434,7 +437,7 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                         if constexpr ((NOISE & NZ_NORMAL) != 0) dxi = g3 * zn[j][dg];
                         full_step<R, DYN, POT, NOISE>(a, path[j], s[j], J[j], gq + col(j),
                                                       fq + col(j), qs, wlen, off, k + (uint32_t)(4 * wd + dg), dxi, h, hh, ngam,
-                                                      A0, A1, Fa, Fb);
+                                                      kp, A0, A1, Fa, Fb);
                     }
                     ++off;
                 }
