@@ -177,7 +177,7 @@ def scan_leg(args):
     res = torch.empty(len(pts) * B.STATS_BYTES, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    tune, tune_ms = B.bm_scan_autotune(models, runs, 2000, ws.data_ptr(), nb, res.data_ptr(), stream.cuda_stream)
+    tune, tune_ms = B.bm_scan_autotune(models, runs, 4000, ws.data_ptr(), nb, res.data_ptr(), stream.cuda_stream)
     t_tune = time.perf_counter() - t0
     h = B.bm_scan_plan_create(models, runs, None, ws.data_ptr(), nb, res.data_ptr(), stream.cuda_stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

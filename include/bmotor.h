@@ -253,9 +253,10 @@ int bm_scan(const bm_model *models, const bm_run *runs, size_t n_points, const b
 
 /* Autotuner: times every launch shape (paths per lane 1/2 for FP32, block 64..512,
  * occupancy-limited groups per CU) on copies of the points with horizons capped at
- * max_steps (window = second half), on `stream`, and stores the fastest in *best
- * (and as the default for this (dyn, pot, noise, prec)).  *best_ms, if not NULL,
- * receives its time.  Synchronises `stream`.  The workspace must fit the scan. */
+ * max_steps (window = second half), on `stream` (one warm-up launch, then the
+ * better of two timed launches per shape), and stores the fastest in *best (and as
+ * the default for this (dyn, pot, noise, prec)).  *best_ms, if not NULL, receives
+ * its time.  Synchronises `stream`.  The workspace must fit the scan. */
 int bm_scan_autotune(const bm_model *models, const bm_run *runs, size_t n_points, uint64_t max_steps,
                      void *d_ws, size_t ws_bytes, bm_stats *d_results, void *stream,
                      bm_tune *best, float *best_ms);

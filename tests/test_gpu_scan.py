@@ -69,6 +69,16 @@ def test_scan_equals_ensembles_bitwise(prec):
         assert g.n == w.n_paths
 
 
+def test_scan_busy_jumps_bitwise():
+    """Kick queues that fill up (lambda dt = 0.5, flips with probability ~0.2 per step) end
+    windows early inside the scan's persistent loop as well."""
+    pts = [w.with_(lam=156.0, mua=60.0, mub=80.0)
+           for w in mixed_points(W.F32, noise=W.GAUSS | W.POISSON | W.DICH)]
+    got = run_scan(pts)
+    for w, g in zip(pts, got):
+        assert stats_bytes(g) == stats_bytes(ensemble_stats(w)), w.name
+
+
 @pytest.mark.parametrize("noise,dyn,pot", [(W.GAUSS | W.DICH, W.OVERDAMPED, W.POT_RATCHET),
                                            (W.POISSON | W.DICH, W.OVERDAMPED, W.POT_TENT)])
 def test_scan_other_models_bitwise(noise, dyn, pot):
