@@ -164,7 +164,7 @@ def host_cpu_model() -> str:
 
 
 def scan_leg(args):
-    """Batched scan of the 4096-point inertial workload: autotune on short horizons,
+    """Batched scan of the 4096-point inertial workload: autotune on scaled-down horizons,
     then one graph launch timed with HIP events on the plan's stream."""
     import torch
     from paper_1409_4923_amd import bmotor as B
@@ -177,7 +177,7 @@ def scan_leg(args):
     res = torch.empty(len(pts) * B.STATS_BYTES, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    tune, tune_ms = B.bm_scan_autotune(models, runs, 4000, ws.data_ptr(), nb, res.data_ptr(), stream.cuda_stream)
+    tune, tune_ms = B.bm_scan_autotune(models, runs, 20000, ws.data_ptr(), nb, res.data_ptr(), stream.cuda_stream)
     t_tune = time.perf_counter() - t0
     h = B.bm_scan_plan_create(models, runs, None, ws.data_ptr(), nb, res.data_ptr(), stream.cuda_stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -385,7 +385,22 @@ def main():
     ap.add_argument("--queries", type=int, default=1_000_000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (for scaling HBM counters) and exit")
+    ap.add_argument("--calibrate-valu", action="store_true",
+                    help="only measure the device's vector-ALU issue rate (FMA chains; FMA + compare + select) "
+                         "against the roofline peak and exit")
     args = ap.parse_args()
+    if args.calibrate_valu:
+        import torch
+        from paper_1409_4923_amd import bmotor as B
+        n = 256 * 32 * 256                        # 32 work-groups of 256 lanes per CU
+        out = torch.empty(n, dtype=torch.float32, device="cuda")
+        stream = torch.cuda.current_stream().cuda_stream
+        rec = {"peak_lane_ops_per_s": VALU_LANE_OPS_PEAK}
+        for mix, name in ((0, "fma"), (1, "fma_cmp_select")):
+            r = B.bm_valu_probe(mix, 20000, out.data_ptr(), n, stream)
+            rec[name] = {"lane_ops_per_s": r, "frac_of_peak": r / VALU_LANE_OPS_PEAK}
+        print(json.dumps({"valu_probe": rec}), flush=True)
+        return
     if args.calibrate_copy:
         import torch
         n = args.calibrate_copy * (1 << 20)

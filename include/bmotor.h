@@ -252,8 +252,9 @@ int bm_scan(const bm_model *models, const bm_run *runs, size_t n_points, const b
             void *d_ws, size_t ws_bytes, bm_stats *d_results, void *stream);
 
 /* Autotuner: times every launch shape (paths per lane 1/2 for FP32, block 64..512,
- * occupancy-limited groups per CU) on copies of the points with horizons capped at
- * max_steps (window = second half), on `stream` (one warm-up launch, then the
+ * occupancy-limited groups per CU) on copies of the points whose horizons are all
+ * scaled by the factor that makes the longest max_steps (each at least 32 steps, none
+ * lengthened; window = second half), on `stream` (one warm-up launch, then the
  * better of two timed launches per shape), and stores the fastest in *best (and as
  * the default for this (dyn, pot, noise, prec)).  *best_ms, if not NULL, receives
  * its time.  Synchronises `stream`.  The workspace must fit the scan. */
@@ -325,6 +326,19 @@ int bm_mlp_adam(uint32_t n_members, float *d_params, const float *d_grad, float 
 int bm_surrogate_query(uint32_t n_members, const float *d_params, const uint16_t *d_wbf, const float *d_x,
                        uint64_t batch, float threshold, float *d_mean, float *d_std, uint32_t *d_fallback_idx,
                        uint32_t *d_fallback_count, void *d_ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Diagnostic (not part of the method): vector-ALU issue rate of the device, the
+ * measured counterpart of the path kernels' roofline peak (one wave64 instruction
+ * per CU per clock).  Runs n_out / 256 work-groups of 256 lanes, each lane
+ * carrying eight independent non-packed FP32 FMA chains for `iters` iterations
+ * (mix 0), or each FMA followed by a compare and a select (mix 1); d_out [n_out]
+ * (device, caller-owned) receives one float per lane.  One warm-up launch, then
+ * the best of three timed launches on `stream`; *lane_ops_per_s = lanes x iters x
+ * 8 x (1 or 3) / time.  Synchronises `stream`.  n_out must be a multiple of 256
+ * in [256, 2^28], iters in [1, 2^24]; otherwise BM_ERR_INVALID_ARG. */
+int bm_valu_probe(uint32_t mix, uint32_t iters, float *d_out, size_t n_out, void *stream,
+                  double *lane_ops_per_s);
 
 #ifdef __cplusplus
 }

@@ -103,6 +103,8 @@ SIGNATURES = [
                                    ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp]),
     ("bm_surrogate_query", ctypes.c_int, [ctypes.c_uint32, _vp, _vp, _vp, ctypes.c_uint64, ctypes.c_float, _vp,
                                           _vp, _vp, _vp, _vp, _sz, _vp]),
+    ("bm_valu_probe", ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, _vp, _sz, _vp,
+                                     ctypes.POINTER(ctypes.c_double)]),
 ]
 
 BM_MLP_INPUTS, BM_MLP_HIDDEN, BM_MLP_PARAMS, BM_MLP_BF16, BM_MLP_MAX_MEMBERS = 5, 256, 133377, 132608, 16
@@ -454,6 +456,14 @@ def bm_surrogate_query(n_members, d_params, d_wbf, d_x, batch, threshold, d_mean
                        ws_bytes, stream) -> None:
     check(lib().bm_surrogate_query(n_members, d_params, d_wbf, d_x, batch, threshold, d_mean, d_std, d_fidx,
                                    d_fcount, d_ws, ws_bytes, stream))
+
+
+def bm_valu_probe(mix: int, iters: int, d_out: int, n_out: int, stream: int) -> float:
+    """Vector-ALU issue rate (lane-ops/s) of the device for mix 0 (FMA chains) or 1
+    (FMA + compare + select); d_out: n_out device floats (a multiple of 256)."""
+    r = ctypes.c_double(0.0)
+    check(lib().bm_valu_probe(mix, iters, d_out, n_out, stream, ctypes.byref(r)))
+    return r.value
 
 
 class Surrogate:

@@ -37,6 +37,7 @@ SOURCES = [
     ("scan_f64_od.hip", []),
     ("scan_f64_in.hip", []),
     ("mlp.hip", []),
+    ("probe.hip", []),
 ]
 
 

@@ -407,8 +407,9 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                     q[j] = U4{0u, 0u, 0u, 0u};
             }
             R A[17];                                  // forcing at steps n .. n+16
+            const R *arow = reinterpret_cast<const R *>(a.tab) + k;   // k + 16 < spp + 16
 #pragma unroll
-            for (int t = 0; t < 17; ++t) A[t] = drive_at<R>(a, k + (uint32_t)t);
+            for (int t = 0; t < 17; ++t) A[t] = arow[t];
 #pragma unroll
             for (int wd = 0; wd < 4; ++wd) {
                 uint32_t u[PPL];

@@ -1,0 +1,79 @@
+// probe.hip -- VALU issue-rate probe for the roofline of the path kernels.
+//
+// The path kernels are bound by vector-ALU issue.  Their roofline peak is derived
+// from the chip's unit counts and clock (one wave64 instruction per CU per clock,
+// 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 lane-ops/s); this probe measures what the
+// device issues for two instruction mixes: eight independent non-packed FP32 FMA
+// chains per lane, and the same with a compare and a select after every FMA (the
+// instruction classes of Algorithm 2's three-point increment).  It is not part of
+// the method.
+#include <hip/hip_runtime.h>
+
+#include "bmotor.h"
+#include "host.hpp"
+
+using namespace bm::host;
+
+namespace {
+
+constexpr int PROBE_CHAINS = 8;
+
+template <int MIX>
+__global__ void __launch_bounds__(256) k_valu_probe(float *out, float a, float b, uint32_t iters)
+{
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float x[PROBE_CHAINS];
+#pragma unroll
+    for (int k = 0; k < PROBE_CHAINS; ++k) x[k] = (float)threadIdx.x * 1e-3f + (float)k;
+    for (uint32_t i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < PROBE_CHAINS; ++k) {
+            x[k] = __builtin_fmaf(x[k], a, b);
+            if constexpr (MIX != 0) x[k] = (x[k] > 0.5f) ? x[k] : b;    // compare + select
+        }
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PROBE_CHAINS; ++k) s += x[k];
+    out[gid] = s;                                                        // keeps the chains live
+}
+
+} // namespace
+
+extern "C" int bm_valu_probe(uint32_t mix, uint32_t iters, float *d_out, size_t n_out, void *stream,
+                             double *lane_ops_per_s)
+{
+    if (mix > 1) return fail(BM_ERR_INVALID_ARG, "mix must be 0 (FMA) or 1 (FMA + compare + select)");
+    if (iters == 0 || iters > (1u << 24)) return fail(BM_ERR_INVALID_ARG, "iters must be in [1, 2^24]");
+    if (!d_out || !lane_ops_per_s) return fail(BM_ERR_INVALID_ARG, "d_out and lane_ops_per_s must not be NULL");
+    if (n_out < 256 || n_out % 256 != 0 || n_out / 256 > (1u << 20))
+        return fail(BM_ERR_INVALID_ARG, "n_out must be a multiple of 256 in [256, 2^28]");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(BM_ERR_DEVICE, "hipEventCreate failed");
+    }
+    const unsigned blocks = (unsigned)(n_out / 256);
+    float best = 0.0f;
+    hipError_t he = hipSuccess;
+    for (int rep = 0; rep < 4 && he == hipSuccess; ++rep) {            // first launch: warm-up
+        he = hipEventRecord(e0, s);
+        if (he == hipSuccess) {
+            if (mix) k_valu_probe<1><<<blocks, 256, 0, s>>>(d_out, 0.999f, 0.001f, iters);
+            else k_valu_probe<0><<<blocks, 256, 0, s>>>(d_out, 0.999f, 0.001f, iters);
+            he = hipGetLastError();
+        }
+        if (he == hipSuccess) he = hipEventRecord(e1, s);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he == hipSuccess && rep > 0 && (rep == 1 || ms < best)) best = ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (he != hipSuccess) return hip_fail(he, "VALU probe");
+    const double ops_per_iter = PROBE_CHAINS * (mix ? 3.0 : 1.0);
+    *lane_ops_per_s = (double)n_out * iters * ops_per_iter / (best * 1e-3);
+    return ok();
+}

@@ -345,11 +345,20 @@ extern "C" int bm_scan_autotune(const bm_model *models, const bm_run *runs, size
     if (rc) return rc;
     if (!best) return fail(BM_ERR_INVALID_ARG, "best must not be NULL");
     if (max_steps < 32) return fail(BM_ERR_INVALID_ARG, "max_steps must be >= 32");
+    // Horizons scaled by one factor so that the longest is max_steps (at least 32
+    // steps each): the timed scans keep the spread of work over the points, which
+    // decides how the persistent grid's tail balances.
     std::vector<bm_run> short_runs(runs, runs + n);
-    for (auto &r : short_runs) {
-        if (r.n_steps > max_steps) {
-            r.n_steps = max_steps;
-            r.window_start = max_steps / 2;
+    uint64_t longest = 0;
+    for (const auto &r : short_runs) longest = r.n_steps > longest ? r.n_steps : longest;
+    if (longest > max_steps) {
+        const double f = (double)max_steps / (double)longest;
+        for (auto &r : short_runs) {
+            uint64_t ns = (uint64_t)std::llround((double)r.n_steps * f);
+            if (ns < 32) ns = 32;
+            if (ns > r.n_steps) ns = r.n_steps;
+            r.n_steps = ns;
+            r.window_start = ns / 2;
         }
     }
     const uint32_t prec = runs[0].prec, noise = models[0].noise;
