@@ -54,8 +54,9 @@ def algorithmic_work(w):
     as they issue to their own unit; flops count an FMA as 2):
       drift evaluation (3 per step): V = sin 2 pi x: cos, 1 FMA; ratchet: cos, 2 FMA;
         tent: mul, floor, FMA, compare, select, add; inertial: + 1 FMA (-gamma v);
-      Algorithm 1: inertial 6 FMA + 5 adds, overdamped 3 FMA + 3 adds (the noise
-        increment is added once), + 1 add for a kick;
+      Algorithm 1: inertial 8 FMA + 1 add, overdamped 4 FMA + 1 add (the noise
+        increment is added once, and the predictor's and corrector's trapezoids
+        share the base y + F1 dt/2), + 1 add for a kick;
       dichotomous level: 1 select + 2 adds; fold: 4 ops per 16 steps;
       Algorithm 2 (three-point): 2 compares + 2 selects + 2 shifts for the next
         base-6 digit + Philox4x32-10 (10 rounds x (2 wide products + 2 three-way
@@ -87,10 +88,10 @@ def algorithmic_work(w):
     flops += 3 * e_fl + 3 * e_tr
     kick = (w.noise & W.POISSON) != 0
     if inertial:
-        ops += 11 + (1 if kick else 0)
+        ops += 9 + (1 if kick else 0)
         flops += 17 + (1 if kick else 0)
     else:
-        ops += 6 + (1 if kick else 0)
+        ops += 5 + (1 if kick else 0)
         flops += 9 + (1 if kick else 0)
     ops += 4.0 / 16.0
     flops += 2.0 / 16.0
@@ -108,7 +109,7 @@ def algorithmic_work(w):
         flops += p_kick * 6
         if w.noise & W.JUMP_GRID:
             piece = 40.0 / 16.0 + 6 if (w.noise & W.GAUSS) else (40.0 / 4.0 + 5 if (w.noise & W.NORMAL) else 0)
-            ops += p_kick * (piece + 30 + 3 + (11 if inertial else 6) + 3 * e_ops)
+            ops += p_kick * (piece + 30 + 3 + (9 if inertial else 5) + 3 * e_ops)
             trans += p_kick * (1 + 3 * e_tr)
             flops += p_kick * (20 + (17 if inertial else 9) + 3 * e_fl)
     if w.noise & W.DICH:
