@@ -164,6 +164,28 @@ def host_cpu_model() -> str:
     return "unknown"
 
 
+FP64_SAMPLE_STEPS = 20000
+
+
+def fp64_rate(w) -> float:
+    """Path-steps/s of the workload with FP64 paths (all paths, FP64_SAMPLE_STEPS steps,
+    timed with HIP events after a 256-step warm-up)."""
+    import torch
+    from paper_1409_4923_amd import bmotor as B
+    from paper_1409_4923_amd import workloads as W
+    w64 = w.with_(prec=W.F64, n_steps=FP64_SAMPLE_STEPS, n_window=0)
+    m, r = W.to_c(w64)
+    e = B.Ensemble(m, r)
+    e.integrate(256)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    e.integrate(FP64_SAMPLE_STEPS)
+    e1.record()
+    torch.cuda.synchronize()
+    return w64.n_paths * FP64_SAMPLE_STEPS / (e0.elapsed_time(e1) / 1e3)
+
+
 def scan_leg(args):
     """Batched scan of the 4096-point inertial workload: autotune on scaled-down horizons,
     then one graph launch timed with HIP events on the plan's stream."""
@@ -520,6 +542,10 @@ def main():
         rec["cpu_baseline"]["single_core"] = {"value": one["value"], "sample": one["sample"]}
         rec["cpu_baseline"]["host_cpu"] = host_cpu_model()
         rec["speedup_vs_one_core"] = value / one["value"]
+        # the same workload with FP64 paths, against the same (FP64) oracle core
+        f64 = fp64_rate(w)
+        rec["fp64_paths"] = {"path_steps_per_s": f64, "speedup_vs_one_core": f64 / one["value"],
+                             "sample": "all %d paths, %d steps" % (w.n_paths, FP64_SAMPLE_STEPS)}
         # the paper's figures (Sec. 6): GPU over the same program on one CPU core
         rec["paper_speedup"] = {"fp32": 3000, "fp64": [700, 400],
                                 "hardware": "NVIDIA GeForce GTX TITAN Black vs one core of an "
