@@ -76,13 +76,53 @@ template <int POT> __device__ __forceinline__ float force_plus(float x, float A,
     }
 }
 
+// cos y in FP64.  Cody-Waite reduction y = k pi/2 + r, k = rint(2y/pi), with pi/2
+// split into three doubles (the first two of 33 significant bits, so k times each is
+// exact for |k| < 2^20), r in [-pi/4, pi/4]; then the Taylor series of sin r to r^17
+// and of cos r to r^16 (remainders below 1e-19 and 3e-18 on that interval), and k
+// mod 4 picks cos r, -sin r, -cos r or sin r.  Arguments with |y| >= 2^20 (or NaN) in
+// any lane of the wave send the whole wave to the library cos.
+__device__ __noinline__ double cos_library(double y) { return cos(y); }
+
+__device__ __forceinline__ double cos_fp64(double y)
+{
+    if (__builtin_amdgcn_ballot_w64(!(fabs(y) < 0x1p20)) != 0) return cos_library(y);
+    const double k = rint(y * 0x1.45f306dc9c883p-1);                 // 2/pi
+    double r = fma(-k, 0x1.921fb544p+0, y);                          // pi/2, first 33 bits
+    r = fma(-k, 0x1.0b4611a6p-34, r);                                //       next 33 bits
+    r = fma(-k, 0x1.3198a2e037073p-69, r);                           //       the rest
+    const double r2 = r * r;
+    // coefficients (-1)^j / n!, n = 2j + 1 (sin) or 2j (cos), rounded to nearest
+    double ps = 0x1.952c77030ad4ap-49;                               //  1/17!
+    ps = fma(ps, r2, -0x1.ae7f3e733b81fp-41);                        // -1/15!
+    ps = fma(ps, r2, 0x1.6124613a86d09p-33);                         //  1/13!
+    ps = fma(ps, r2, -0x1.ae64567f544e4p-26);                        // -1/11!
+    ps = fma(ps, r2, 0x1.71de3a556c734p-19);                         //  1/9!
+    ps = fma(ps, r2, -0x1.a01a01a01a01ap-13);                        // -1/7!
+    ps = fma(ps, r2, 0x1.1111111111111p-7);                          //  1/5!
+    ps = fma(ps, r2, -0x1.5555555555555p-3);                         // -1/3!
+    const double sn = fma(r * r2, ps, r);
+    double pc = 0x1.ae7f3e733b81fp-45;                               //  1/16!
+    pc = fma(pc, r2, -0x1.93974a8c07c9dp-37);                        // -1/14!
+    pc = fma(pc, r2, 0x1.1eed8eff8d898p-29);                         //  1/12!
+    pc = fma(pc, r2, -0x1.27e4fb7789f5cp-22);                        // -1/10!
+    pc = fma(pc, r2, 0x1.a01a01a01a01ap-16);                         //  1/8!
+    pc = fma(pc, r2, -0x1.6c16c16c16c17p-10);                        // -1/6!
+    pc = fma(pc, r2, 0x1.5555555555555p-5);                          //  1/4!
+    pc = fma(pc, r2, -0.5);                                          // -1/2!
+    const double cs = fma(r2, pc, 1.0);
+    const int q = (int)k & 3;                                        // k mod 4 (two's complement)
+    const double v = (q & 1) ? sn : cs;
+    return (q == 1 || q == 2) ? -v : v;
+}
+
 template <int POT> __device__ __forceinline__ double force_plus(double x, double A, double kp)
 {
     constexpr double PI = 3.14159265358979323846;
     if constexpr (POT == POT_SIN) {
-        return fma(kp, cos(2.0 * PI * x), A);
+        return fma(kp, cos_fp64(2.0 * PI * x), A);
     } else if constexpr (POT == POT_RATCHET) {
-        const double c = cos(2.0 * PI * x);
+        const double c = cos_fp64(2.0 * PI * x);
         return fma(c, fma(kp, c, kp), A);                                 // A includes -pi
     } else if constexpr (POT == POT_TENT) {
         const double y = x - 2.0 * floor(x / 2.0);
