@@ -190,9 +190,10 @@ template <int POT, typename R> __device__ __forceinline__ void fold(Path<R> &s)
 // offset with the next queued offset.  The window (16 2^k steps, at most 1024) is
 // chosen per parameter point so that a lane expects about four jumps in it: the
 // wave-uniform loop runs as many iterations as the lane with the most jumps, and
-// a queue rarely fills up.  A full kick queue ends the window early for the whole
-// wave (at the first kick it does not hold); a lane with more than JCAP flips in a
-// window queues an "inline" marker and draws the rest at their steps.
+// a queue rarely fills up.  On the fixed grid a full queue ends the window early for
+// the whole wave (at the first jump it does not hold); on the jump-adapted grid a
+// lane with more than JCAP flips in a window queues an "inline" marker and draws
+// the rest at their steps.
 // ---------------------------------------------------------------------------
 constexpr uint32_t JCAP = 11;         // queued jumps per lane and window
 constexpr uint32_t INLINE_BIT = 0x80000000u;
@@ -337,10 +338,12 @@ __device__ __forceinline__ uint32_t queued_beyond(const T *q, uint32_t qs, uint3
     return c;
 }
 
-// Queue the flips of one window; bit INLINE_BIT marks "draw inline from here".
+// Queue the flips of one window; bit INLINE_BIT marks "draw inline from here" (only
+// the jump-adapted grid runs past it; on the fixed grid a full queue ends the window,
+// as for kicks).  Returns the number of leading steps whose flips are all queued.
 template <typename R>
-__device__ __forceinline__ void flip_window(const PointConst &a, uint32_t path, uint32_t wlen, uint32_t off,
-                                            uint32_t &mD, int32_t d, uint32_t *q, uint32_t qs)
+__device__ __forceinline__ uint32_t flip_window(const PointConst &a, uint32_t path, uint32_t wlen, uint32_t off,
+                                                uint32_t &mD, int32_t d, uint32_t *q, uint32_t qs)
 {
     uint32_t slot = 0;
     bool active = off < wlen;
@@ -359,7 +362,9 @@ __device__ __forceinline__ void flip_window(const PointConst &a, uint32_t path, 
             }
         }
     }
-    q[slot * qs] = (slot == JCAP && off < wlen) ? (off | INLINE_BIT) : off;
+    const bool full = slot == JCAP && off < wlen;
+    q[slot * qs] = full ? (off | INLINE_BIT) : off;
+    return full ? off : wlen;
 }
 
 // ---------------------------------------------------------------------------

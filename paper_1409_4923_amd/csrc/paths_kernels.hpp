@@ -236,7 +236,12 @@ __device__ __forceinline__ void full_step(const PointConst &a, uint32_t path, Pa
     if constexpr ((NOISE & NZ_DICH) != 0) {
         if (J.nD == off) {                       // Algorithm 4: s <= 0 at this step
             s.d = 1 - s.d;
-            if (J.cD != FLIP_INLINE) {
+            if constexpr ((NOISE & NZ_JGRID) == 0) {
+                // the window ends before a full queue's marker: every flip is queued
+                const uint32_t e = fq[J.cD];
+                J.cD += qs;
+                J.nD = e & ~INLINE_BIT;
+            } else if (J.cD != FLIP_INLINE) {
                 const uint32_t e = fq[J.cD];
                 J.cD += qs;
                 if (e & INLINE_BIT) J.cD = FLIP_INLINE;
@@ -332,16 +337,18 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                 J[j].pP = kq + col(j) + qs;
             }
             if constexpr ((NOISE & NZ_DICH) != 0) {
-                flip_window<R>(a, path[j], wlen, (uint32_t)s[j].sD, s[j].mD, s[j].d, fq + col(j), qs);
+                const uint32_t c = flip_window<R>(a, path[j], wlen, (uint32_t)s[j].sD, s[j].mD, s[j].d,
+                                                  fq + col(j), qs);
+                if constexpr ((NOISE & NZ_JGRID) == 0) cover = c < cover ? c : cover;
                 const uint32_t e = fq[col(j)];
                 J[j].nD = e & ~INLINE_BIT;
                 J[j].cD = (e & INLINE_BIT) ? FLIP_INLINE : qs;
             }
         }
-        if constexpr (queued_kicks<NOISE>()) {
-            // A full kick queue ends the window for the wave at the first kick it
-            // does not hold (the minimum over the lanes, at least JCAP steps in),
-            // rounded down to a 16-step block boundary when one lies after n.
+        if constexpr (queued_kicks<NOISE>() || (NOISE & (NZ_DICH | NZ_JGRID)) == NZ_DICH) {
+            // A full kick or flip queue ends the window for the wave at the first
+            // jump it does not hold (the minimum over the lanes, at least JCAP steps
+            // in), rounded down to a 16-step block boundary when one lies after n.
             if (__any(cover < wlen)) {
                 uint32_t wl = wlen;
                 for (;;) {
@@ -468,7 +475,7 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
             }
             if constexpr ((NOISE & NZ_DICH) != 0) {
                 s[j].sD = (int32_t)(J[j].nD - wlen);
-                if (queued_kicks<NOISE>() && early)
+                if ((NOISE & NZ_JGRID) == 0 && early)
                     s[j].mD -= queued_beyond(fq + col(j), qs, wlen, wdrawn, [](uint32_t e) { return e; });
             }
         }
