@@ -40,10 +40,10 @@ FP64_PEAK_FLOPS = 78.6e12
 # reads 0.5 GiB for it: factor 2.0; WRITE_SIZE reads 1 GiB: factor 1.0).  Valid
 # only while the integration kernel's sources hash to KERNEL_SOURCES_SHA256.
 TRAFFIC_WORKLOAD = "inertial-poisson-f32-2^20"
-TRAFFIC_BYTES_PER_LAUNCH = ((10553.0625 + 10327.0) / 2 * 2.0 + (28672.0 + 20480.0) / 2 * 1.0) * 1024
+TRAFFIC_BYTES_PER_LAUNCH = ((10524.0625 + 10327.0) / 2 * 2.0 + (28672.0 + 20480.0) / 2 * 1.0) * 1024
 KERNEL_SOURCES = ("common.hpp", "paths.hpp", "paths_kernels.hpp", "paths_tu.inc", "paths_f32_in.hip",
                   "launch.hpp")
-KERNEL_SOURCES_SHA256 = "956dd1c2ad79f01a32b39fdc4c7013ec948faf42fdaa4b00d9a43e4c8fd68a14"
+KERNEL_SOURCES_SHA256 = "e5b7cb09b6cad74670e1eaecdcaa9c1e43f3903a34a9114e6d6a8845682ab00f"
 
 
 def algorithmic_work(w):
