@@ -264,7 +264,8 @@ int bm_scan_autotune(const bm_model *models, const bm_run *runs, size_t n_points
 
 /* Default launch shape per (dyn, pot, noise, prec) for this process (used when
  * a call gets no bm_tune); the built-in default is 1 path per lane, block 256,
- * groups_per_cu 0. */
+ * groups_per_cu 0, except FP32 inertial models without Poisson or dichotomous
+ * noise: 2 paths per lane, block 128. */
 int bm_tune_set_default(uint32_t dyn, uint32_t pot, uint32_t noise, uint32_t prec, const bm_tune *tune);
 int bm_tune_get_default(uint32_t dyn, uint32_t pot, uint32_t noise, uint32_t prec, bm_tune *out);
 

@@ -254,8 +254,13 @@ def test_scan_workspace_and_validation():
 
 
 def test_tune_defaults_roundtrip_and_checks():
+    # built-in: two paths per lane for FP32 inertial models without jump processes
     t = B.bm_tune_get_default(W.INERTIAL, W.POT_SIN, W.GAUSS, W.F32)
-    assert (t.paths_per_lane, t.block, t.groups_per_cu) == (1, 256, 0)
+    assert (t.paths_per_lane, t.block, t.groups_per_cu) == (2, 128, 0)
+    for dyn, noise, prec in ((W.INERTIAL, W.GAUSS | W.POISSON, W.F32), (W.OVERDAMPED, W.GAUSS, W.F32),
+                             (W.INERTIAL, W.GAUSS, W.F64), (W.OVERDAMPED, W.GAUSS | W.DICH, W.F32)):
+        t = B.bm_tune_get_default(dyn, W.POT_SIN, noise, prec)
+        assert (t.paths_per_lane, t.block, t.groups_per_cu) == (1, 256, 0)
     B.bm_tune_set_default(W.INERTIAL, W.POT_SIN, W.GAUSS, W.F32, B.make_tune(2, 128, 3))
     t = B.bm_tune_get_default(W.INERTIAL, W.POT_SIN, W.GAUSS, W.F32)
     assert (t.paths_per_lane, t.block, t.groups_per_cu) == (2, 128, 3)
