@@ -673,3 +673,115 @@ def test_jump_grid_chunked_equals_whole(orc):
     orc.advance(P, b, 100, 0, 377)
     orc.advance(P, b, 100, 377, 1000)
     assert a.tobytes() == b.tobytes()
+
+
+def _fixed_grid_kick_steps(orc, P, path, n_steps):
+    """Steps of the fixed-grid kicks of one path and their amplitudes, written out
+    from the Philox words: the countdown starts at floor(E0 / (lambda dt)) and a kick
+    at step n (countdown at 0) draws the next countdown from its own words."""
+    key = (P.seed & 0xFFFFFFFF, P.seed >> 32)
+    E = lambda w: -math.log(1.0 - w * 2.0 ** -32)
+    lam_dt = P.lam * P.step()
+    n = math.floor(E(orc.philox4x32_10((0, path, P.point, 2), key)[2]) / lam_dt)
+    out = []
+    k = 0
+    while n < n_steps:
+        J = orc.philox4x32_10((k // 2, path, P.point, 1), key)
+        half = k % 2
+        out.append((n, P.zeta * E(J[2 * half + 1])))
+        n += 1 + math.floor(E(J[2 * half]) / lam_dt)
+        k += 1
+    return out
+
+
+def _harmonic_driven_kicked_exact(P, x0, T, kicks):
+    """x' = -k x + a cos(omega t) + F - lambda zeta + sum_i z_i delta(t - t_i), exactly:
+    x0 e^{-kT} + c (1 - e^{-kT}) / k + a (k cos wT + w sin wT - k e^{-kT}) / (k^2 + w^2)
+    + sum_i z_i e^{-k (T - t_i)}, c = F - lambda zeta."""
+    k, w, a = P.k_harm, P.omega, P.a
+    c = P.F - P.lam * P.zeta
+    e = math.exp(-k * T)
+    x = x0 * e + c * (1.0 - e) / k + a * (k * math.cos(w * T) + w * math.sin(w * T) - k * e) / (k * k + w * w)
+    for t, z in kicks:
+        x += z * math.exp(-k * (T - t))
+    return x
+
+
+def test_jump_grid_drive_inside_split_steps(orc):
+    """Linear drift, periodic drive (integer phase, spp > 0) and kicks on the
+    jump-adapted grid: a piece that ends at a kick at t_n + theta dt takes the drive at
+    that time, a cos(2 pi (n + theta) / spp) + F.  Against the exact solution the
+    global error falls about 4x per halving of dt; with the drive taken anywhere else
+    inside a split step (a phase error of order one) it would be first order."""
+    errs = []
+    for spp in (64, 128, 256):
+        P = orc.Params(pot=orc.POT_HARMONIC, k_harm=1.1, noise=orc.POISSON | orc.JUMP_GRID, lam=3.0, zeta=0.4,
+                       a=2.5, omega=4.0, F=0.3, spp=spp, seed=21, x0_lo=-1.0, x0_hi=1.0)
+        n = 3 * spp                                   # three drive periods
+        T = n * P.step()
+        st0 = orc.init(P, 0, 24)
+        st = orc.advance(P, st0.copy(), 0, 0, n)
+        e = []
+        for p in range(24):
+            kicks = _kick_times(orc, P, p, T)
+            assert st["kP"][p] == len(kicks)
+            e.append(abs(st["x"][p] - _harmonic_driven_kicked_exact(P, st0["x"][p], T, kicks)))
+        errs.append(max(e))
+    assert errs[0] / errs[1] > 3.3 and errs[1] / errs[2] > 3.3
+    assert errs[2] < 2e-4
+
+
+def _inertial_free_exact(P, x0, v0, T, kicks):
+    """v' = -gamma v + a cos(omega t) + F - lambda zeta + sum_i z_i delta(t - t_i), x' = v,
+    exactly (the kicks act on v):
+    v(T) = v0 e^{-gT} + a (g cos wT + w sin wT - g e^{-gT}) / (g^2 + w^2) + c (1 - e^{-gT}) / g
+           + sum_i z_i e^{-g (T - t_i)},
+    x(T) = x0 + v0 (1 - e^{-gT}) / g + a (g sin(wT) / w + (1 - cos wT) - (1 - e^{-gT})) / (g^2 + w^2)
+           + c (T - (1 - e^{-gT}) / g) / g + sum_i z_i (1 - e^{-g (T - t_i)}) / g."""
+    g, w, a = P.gamma, P.omega, P.a
+    c = P.F - P.lam * P.zeta
+    e = math.exp(-g * T)
+    d2 = g * g + w * w
+    v = v0 * e + a * (g * math.cos(w * T) + w * math.sin(w * T) - g * e) / d2 + c * (1.0 - e) / g
+    x = (x0 + v0 * (1.0 - e) / g + a * (g * math.sin(w * T) / w + (1.0 - math.cos(w * T)) - (1.0 - e)) / d2
+         + c * (T - (1.0 - e) / g) / g)
+    for t, z in kicks:
+        ek = math.exp(-g * (T - t))
+        v += z * ek
+        x += z * (1.0 - ek) / g
+    return x, v
+
+
+def test_inertial_kicks_act_on_velocity(orc):
+    """Inertial free particle with periodic drive and Poisson kicks, no Gaussian noise.
+    The kick of Algorithm 3 jumps v (never x).  Jump-adapted grid: kicks at their exact
+    times, x(T) and v(T) converge at second order.  Fixed grid: the kick of step n is
+    added at the end of the step, i.e. at t_{n+1}; against the exact solution with the
+    kicks at those times the error is second order too."""
+    errs = {}
+    for mode in (orc.POISSON | orc.JUMP_GRID, orc.POISSON):
+        errs[mode] = []
+        for spp in (50, 100, 200):
+            P = orc.Params(dyn=orc.INERTIAL, pot=orc.POT_FREE, noise=mode, gamma=0.8, lam=2.5, zeta=0.6,
+                           a=1.5, omega=3.0, F=0.2, spp=spp, seed=33, x0_lo=0.0, x0_hi=1.0,
+                           v0_lo=-1.0, v0_hi=1.0)
+            n = 4 * spp
+            dt = P.step()
+            T = n * dt
+            st0 = orc.init(P, 0, 24)
+            x0 = orc.unwrapped(P, st0)
+            st = orc.advance(P, st0.copy(), 0, 0, n)
+            xT = orc.unwrapped(P, st)
+            e = []
+            for p in range(24):
+                if mode & orc.JUMP_GRID:
+                    kicks = _kick_times(orc, P, p, T)
+                else:
+                    kicks = [((m + 1) * dt, z) for m, z in _fixed_grid_kick_steps(orc, P, p, n)]
+                assert st["kP"][p] == len(kicks) and len(kicks) > 0
+                xe, ve = _inertial_free_exact(P, x0[p], st0["v"][p], T, kicks)
+                e.append(max(abs(xT[p] - xe), abs(st["v"][p] - ve)))
+            errs[mode].append(max(e))
+    for mode, er in errs.items():
+        assert er[0] / er[1] > 3.3 and er[1] / er[2] > 3.3, (mode, er)
+        assert er[2] < 1e-4, (mode, er)
