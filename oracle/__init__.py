@@ -54,12 +54,13 @@ class _Params(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("point", ctypes.c_uint32), ("pad", ctypes.c_uint32),
         ("x0_lo", ctypes.c_double), ("x0_hi", ctypes.c_double),
         ("v0_lo", ctypes.c_double), ("v0_hi", ctypes.c_double),
+        ("step_tol", ctypes.c_double), ("max_halvings", ctypes.c_int32), ("pad2", ctypes.c_int32),
     ]
 
 
 PATH_DTYPE = np.dtype([("x", "<f8"), ("w", "<i8"), ("v", "<f8"), ("xi", "<f8"), ("wi", "<i8"),
                        ("sP", "<i8"), ("thP", "<f8"), ("kP", "<u8"), ("sD", "<i8"), ("mD", "<u8"),
-                       ("d", "<i4"), ("pad", "<i4")])
+                       ("d", "<i4"), ("lev", "<i4"), ("kA", "<u8")])
 
 _lib = None
 
@@ -81,6 +82,9 @@ def lib():
         L.or_init.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
         L.or_advance.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint64, ctypes.c_uint64,
                                  ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]
+        L.or_advance_adaptive.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint64, ctypes.c_uint64,
+                                          ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]
+        L.or_advance_adaptive.restype = ctypes.c_int
         L.or_velocity.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint64, ctypes.c_void_p,
                                   ctypes.c_int64, ctypes.c_void_p]
         L.or_unwrapped.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint64, ctypes.c_void_p,
@@ -106,6 +110,8 @@ class Params:
     Poisson (eqs. 3-6): lam, zeta.  Dichotomous (eqs. 13-14): levels -Fa / +Fb,
     leaving rates mua (of -Fa) and mub (of +Fb).
     spp > 0: dt = (2 pi / omega) / spp unless dt is given; drive phase = n mod spp.
+    step_tol > 0: step-size control on chi with steps dt / 2^j, j <= max_halvings, one
+    controller per group of 64 consecutive paths (Gaussian noise only).
     """
     dyn: int = OVERDAMPED
     pot: int = POT_SIN
@@ -132,6 +138,8 @@ class Params:
     v0_lo: float = 0.0
     v0_hi: float = 0.0
     literal_alg1: bool = False
+    step_tol: float = 0.0
+    max_halvings: int = 0
 
     def period(self) -> float:
         return 2.0 if self.pot == POT_TENT else 1.0
@@ -151,6 +159,7 @@ class Params:
         p.dt = self.step()
         p.spp, p.n_window, p.seed, p.point = self.spp, self.n_window, self.seed, self.point
         p.x0_lo, p.x0_hi, p.v0_lo, p.v0_hi = self.x0_lo, self.x0_hi, self.v0_lo, self.v0_hi
+        p.step_tol, p.max_halvings = self.step_tol, self.max_halvings
         return p
 
 
@@ -222,8 +231,42 @@ def advance(params: Params, st: np.ndarray, first_path: int, n_from: int, n_to: 
     return st
 
 
-def run(params: Params, first_path: int, count: int, n_steps: int, threads: int = 1) -> np.ndarray:
+def advance_adaptive(params: Params, st: np.ndarray, first_path: int, n_paths: int, n_from: int, n_to: int,
+                     threads: int = 1) -> np.ndarray:
+    """Step-controlled advance (params.step_tol > 0) of paths first_path .. (whole
+    groups of 64 of an ensemble of n_paths) from step n_from to n_to, in place."""
+    assert st.dtype == PATH_DTYPE and st.flags.c_contiguous
+    cp = params.c()
+    L = lib()
+    groups = (len(st) + 63) // 64
+
+    def run_groups(g0, g1):
+        lo, hi = 64 * g0, min(64 * g1, len(st))
+        rc = L.or_advance_adaptive(ctypes.byref(cp), first_path + lo, hi - lo, n_paths, n_from, n_to,
+                                   st.ctypes.data + lo * PATH_DTYPE.itemsize)
+        if rc != 0:
+            raise ValueError("step control needs whole groups of 64 paths starting at a multiple of 64")
+
+    parts = _split(groups, threads)
+    if len(parts) == 1:
+        run_groups(*parts[0])
+    else:
+        ts = [threading.Thread(target=run_groups, args=pr) for pr in parts]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+    return st
+
+
+def run(params: Params, first_path: int, count: int, n_steps: int, threads: int = 1,
+        n_paths: int | None = None) -> np.ndarray:
+    """Paths first_path .. first_path + count - 1 after n_steps steps of dt.  With step
+    control, n_paths (default first_path + count) is the ensemble size that closes the
+    last group."""
     st = init(params, first_path, count)
+    if params.step_tol > 0:
+        return advance_adaptive(params, st, first_path, n_paths or first_path + count, 0, n_steps, threads)
     return advance(params, st, first_path, 0, n_steps, threads)
 
 

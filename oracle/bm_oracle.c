@@ -19,7 +19,7 @@
  *   - Algorithm 4 / eqs. (13)-(14), (29)-(30): dichotomous increment;
  *   - Algorithm 1: predictor-corrector step for eq. (24) (and the inertial
  *     extension x'' + gamma x' = ... used by the benchmark workloads);
- *   - Sec. 4 "Instruction optimization": folding of x modulo L;
+ *   - Sec. 5 "Instruction optimization": folding of x modulo L;
  *   - eq. (31): time-averaged velocity estimator per path.
  *
  * Readings where the paper is silent (all shared with the HIP path and listed
@@ -140,6 +140,9 @@ typedef struct {
     uint32_t point;
     uint32_t pad;
     double x0_lo, x0_hi, v0_lo, v0_hi;
+    double step_tol;           /* step control on chi (0: fixed step dt)          */
+    int32_t max_halvings;      /* step control: smallest step dt / 2^max_halvings */
+    int32_t pad2;
 } or_params;
 
 typedef struct {
@@ -154,7 +157,8 @@ typedef struct {
     int64_t sD;     /* Algorithm 4 countdown                           */
     uint64_t mD;    /* dichotomous flips so far                        */
     int32_t d;      /* Algorithm 4 state: 0 -> -Fa, 1 -> +Fb           */
-    int32_t pad;
+    int32_t lev;    /* step control: current step is dt / 2^lev        */
+    uint64_t kA;    /* step control: steps taken (index of the Algorithm 2 draw) */
 } or_path;
 
 static const double PI = 3.14159265358979323846;
@@ -184,6 +188,7 @@ static double expo_from_word(uint32_t w)
 /* ------------------------------------------------------------------------ */
 int or_three_point(const or_params *P, uint64_t path, int64_t n)
 {
+    /* the n-th draw of the path's tag-0 stream */
     uint32_t w[4];
     draw(P, (uint32_t)(n / 16), path, 0u, w);
     uint32_t u = w[(n % 16) / 4];
@@ -311,6 +316,8 @@ void or_init(const or_params *P, uint64_t first_path, uint64_t count, or_path *o
             s->d = 1 - dstar;     /* step 0 flips into dstar and draws its dwell */
             s->sD = 0;
         }
+        /* step control starts from the smallest step and lets chi coarsen it */
+        if (P->step_tol > 0) s->lev = P->max_halvings;
         if (P->n_window == 0) { s->xi = s->x; s->wi = s->w; }
     }
 }
@@ -322,7 +329,7 @@ void or_init(const or_params *P, uint64_t first_path, uint64_t count, or_path *o
 /* as-printed variant's extra forcing increment (R1).                         */
 /* ------------------------------------------------------------------------ */
 static void predictor_corrector(const or_params *P, double *px, double *pv, double h, double dxi,
-                                double z, double c, double lit, double A0, double A1)
+                                double z, double c, double lit, double A0, double A1, double *chi)
 {
     double x = *px, v = *pv;
     double F1x, F1v, F2x, F2v;
@@ -337,6 +344,8 @@ static void predictor_corrector(const or_params *P, double *px, double *pv, doub
         drift(P, xb, vb, A1, c, &F2x, &F2v);
         double xn = x + 0.5 * (F1x + F2x) * h;        /* corrector */
         double vn = v + 0.5 * (F1v + F2v) * h + dxi + z;
+        /* local error estimate: predictor minus corrector (before the kick) */
+        if (chi) *chi = fmax(fabs(xb - xn), fabs(vb - (vn - z)));
         vn += lit * h;
         *px = xn; *pv = vn;
     } else {
@@ -345,6 +354,7 @@ static void predictor_corrector(const or_params *P, double *px, double *pv, doub
         xb = x + 0.5 * (F1x + F2x) * h + dxi;         /* predictor */
         drift(P, xb, v, A1, c, &F2x, &F2v);
         double xn = x + 0.5 * (F1x + F2x) * h + dxi + z; /* corrector */
+        if (chi) *chi = fabs(xb - (xn - z));
         xn += lit * h;
         *px = xn;
     }
@@ -381,6 +391,46 @@ static double kick_interval_noise(const or_params *P, uint64_t path, uint64_t k)
     return 0.0;
 }
 
+/* Algorithm 4 at one step of dt: flip and draw the new dwell when the countdown
+ * has run out, else count down.  Returns the level Gamma over the step. */
+static double dichotomous_step(const or_params *P, uint64_t path, or_path *s)
+{
+    if (!(P->noise & OR_DICH)) return 0.0;
+    const double h = P->dt;
+    if (s->sD <= 0) {
+        uint32_t K[4];
+        draw(P, (uint32_t)(s->mD / 4), path, 3u, K);
+        s->d = 1 - s->d;
+        double mu = s->d ? P->mub : P->mua;   /* rate of leaving the new state */
+        s->sD = (int64_t)floor(expo_from_word(K[s->mD % 4]) / (mu * h));
+        s->mD += 1;
+    } else {
+        s->sD -= 1;
+    }
+    return s->d ? P->Fb : -P->Fa;
+}
+
+/* Algorithm 3 on the fixed grid (R3) at one step of dt: when the countdown has run
+ * out, the kick amplitude z (added at the end of the step) and the next countdown;
+ * else count down and z = 0. */
+static double poisson_fixed_step(const or_params *P, uint64_t path, or_path *s)
+{
+    if (!(P->noise & OR_POISSON)) return 0.0;
+    const double h = P->dt;
+    double z = 0.0;
+    if (s->sP <= 0) {
+        uint32_t J[4];
+        draw(P, (uint32_t)(s->kP / 2), path, 1u, J);
+        int half = (int)(s->kP % 2);
+        s->sP = (int64_t)floor(expo_from_word(J[2 * half]) / (P->lambda * h));
+        z = P->zeta * expo_from_word(J[2 * half + 1]);
+        s->kP += 1;
+    } else {
+        s->sP -= 1;
+    }
+    return z;
+}
+
 /* ------------------------------------------------------------------------ */
 /* One step n -> n+1 of one path.                                            */
 /* ------------------------------------------------------------------------ */
@@ -400,20 +450,7 @@ static void step(const or_params *P, uint64_t path, int64_t n, or_path *s)
     }
 
     /* Algorithm 4: dichotomous increment (constant over the step). */
-    double Gam = 0.0;
-    if (P->noise & OR_DICH) {
-        if (s->sD <= 0) {
-            uint32_t K[4];
-            draw(P, (uint32_t)(s->mD / 4), path, 3u, K);
-            s->d = 1 - s->d;
-            double mu = s->d ? P->mub : P->mua;   /* rate of leaving the new state */
-            s->sD = (int64_t)floor(expo_from_word(K[s->mD % 4]) / (mu * h));
-            s->mD += 1;
-        } else {
-            s->sD -= 1;
-        }
-        Gam = s->d ? P->Fb : -P->Fa;
-    }
+    double Gam = dichotomous_step(P, path, s);
 
     double bias = (P->noise & OR_POISSON) ? P->lambda * P->zeta : 0.0;
 
@@ -424,7 +461,7 @@ static void step(const or_params *P, uint64_t path, int64_t n, or_path *s)
         double c = Gam - bias;
         if (s->sP > 0) {
             s->sP -= 1;
-            predictor_corrector(P, &s->x, &s->v, h, dxi, 0.0, c, 0.0, drive(P, n), drive(P, n + 1));
+            predictor_corrector(P, &s->x, &s->v, h, dxi, 0.0, c, 0.0, drive(P, n), drive(P, n + 1), NULL);
         } else {
             double from = 0.0, u = unit;
             double A_from = drive(P, n);
@@ -438,7 +475,7 @@ static void step(const or_params *P, uint64_t path, int64_t n, or_path *s)
                 draw(P, (uint32_t)(s->kP / 2), path, 1u, J);
                 int half = (int)(s->kP % 2);
                 double z = P->zeta * expo_from_word(J[2 * half + 1]);
-                predictor_corrector(P, &s->x, &s->v, hs, u * scale, z, c, 0.0, A_from, A_th);
+                predictor_corrector(P, &s->x, &s->v, hs, u * scale, z, c, 0.0, A_from, A_th, NULL);
                 /* next kick time, counted from this one */
                 double T = th + expo_from_word(J[2 * half]) / (P->lambda * h);
                 u = kick_interval_noise(P, path, s->kP);
@@ -452,31 +489,19 @@ static void step(const or_params *P, uint64_t path, int64_t n, or_path *s)
             /* last piece, to the end of the step */
             double hs = (1.0 - from) * h;
             double scale = (P->noise & OR_GAUSS) ? noise_G(P) * sqrt(3.0 * hs) : noise_G(P) * sqrt(hs);
-            predictor_corrector(P, &s->x, &s->v, hs, u * scale, 0.0, c, 0.0, A_from, drive(P, n + 1));
+            predictor_corrector(P, &s->x, &s->v, hs, u * scale, 0.0, c, 0.0, A_from, drive(P, n + 1), NULL);
             s->sP -= 1;
         }
     } else {
         /* Algorithm 3: Poissonian increment on the fixed grid (R3). */
-        double z = 0.0;
-        if (P->noise & OR_POISSON) {
-            if (s->sP <= 0) {
-                uint32_t J[4];
-                draw(P, (uint32_t)(s->kP / 2), path, 1u, J);
-                int half = (int)(s->kP % 2);
-                s->sP = (int64_t)floor(expo_from_word(J[2 * half]) / (P->lambda * h));
-                z = P->zeta * expo_from_word(J[2 * half + 1]);
-                s->kP += 1;
-            } else {
-                s->sP -= 1;
-            }
-        }
+        double z = poisson_fixed_step(P, path, s);
         /* Algorithm 1: predictor-corrector. */
         double c = P->literal_alg1 ? 0.0 : (Gam - bias);
         double lit = P->literal_alg1 ? (Gam - bias) : 0.0;
-        predictor_corrector(P, &s->x, &s->v, h, dxi, z, c, lit, drive(P, n), drive(P, n + 1));
+        predictor_corrector(P, &s->x, &s->v, h, dxi, z, c, lit, drive(P, n), drive(P, n + 1), NULL);
     }
 
-    fold(P, s);                                     /* x mod L (Sec. 4) */
+    fold(P, s);                                     /* x mod L (Sec. 5) */
     if (n + 1 == P->n_window) { s->xi = s->x; s->wi = s->w; }
 }
 
@@ -487,6 +512,108 @@ void or_advance(const or_params *P, uint64_t first_path, uint64_t count,
     for (uint64_t i = 0; i < count; ++i)
         for (int64_t n = n_from; n < n_to; ++n)
             step(P, first_path + i, n, &st[i]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step-size control on chi (the paragraph after Algorithm 1: the difference  */
+/* chi between predictor and corrector estimates the local error and may      */
+/* steer the step size).  Our reading (the paper gives no controller):        */
+/*  - steps are dt / 2^lev, 0 <= lev <= max_halvings (starting from the      */
+/*    smallest), so every time reached                                         */
+/*    lies on the grid of dt / 2^max_halvings and no step straddles a          */
+/*    multiple of dt (a step may double only where the doubled step starts on  */
+/*    its own grid);                                                           */
+/*  - one controller serves a group of 64 consecutive paths (64 g ..          */
+/*    64 g + 63, those below n_paths): after each step e = the largest         */
+/*    max(|chi_x|, |chi_v|) over the group; e > tol halves the next step,     */
+/*    e < tol / 16 doubles it (where allowed), otherwise it is kept;          */
+/*  - every step is accepted (no rejection, so no sampling bias from           */
+/*    redrawing), and step k of a path (counting steps of any size) takes      */
+/*    the k-th three-point draw of its tag-0 stream scaled by G sqrt(3 h);     */
+/*    without refinement this is the fixed-step scheme draw for draw;          */
+/*  - the drive at t = (n + u / 2^J) dt is a cos(2 pi ((n mod spp) 2^J + u) /  */
+/*    (spp 2^J)) + F, J = max_halvings;                                        */
+/*  - the jump processes stay on the dt grid (Algorithms 3 and 4 as in the    */
+/*    fixed-step scheme): the dichotomous level and the Poisson bias are       */
+/*    drift over the whole interval [n dt, (n+1) dt), whatever its sub-steps,  */
+/*    and a kick drawn at step n is added after its last sub-step; chi never   */
+/*    includes the kick.  Normal increments and the jump-adapted grid are not  */
+/*    combined with step control.                                              */
+/* ------------------------------------------------------------------------ */
+static double drive_sub(const or_params *P, int64_t n, int64_t u, int J)
+{
+    if (P->spp <= 0) return P->F;
+    double scale = ldexp(1.0, J);
+    double k = (double)(n % P->spp) * scale + (double)u;
+    return P->a * cos(2.0 * PI * k / ((double)P->spp * scale)) + P->F;
+}
+
+/* Advance the group of paths st[0 .. count-1] (paths first_path .., one control
+ * group: count <= 64) over the steps n_from .. n_to of length dt. */
+static void advance_group(const or_params *P, uint64_t first_path, uint64_t count,
+                          int64_t n_from, int64_t n_to, or_path *st)
+{
+    const int J = P->max_halvings;
+    const int64_t full = (int64_t)1 << J;              /* one dt in grid units */
+    const double G = noise_G(P);
+    const double bias = (P->noise & OR_POISSON) ? P->lambda * P->zeta : 0.0;
+    double chi[64], c[64], z[64];
+    for (int64_t n = n_from; n < n_to; ++n) {
+        for (uint64_t i = 0; i < count; ++i) {           /* jumps of this step of dt */
+            double Gam = dichotomous_step(P, first_path + i, &st[i]);
+            z[i] = poisson_fixed_step(P, first_path + i, &st[i]);
+            c[i] = Gam - bias;
+        }
+        int64_t u = 0;                                 /* position inside [n, n+1) */
+        while (u < full) {
+            const int lev = st[0].lev;                 /* shared by the group */
+            const int64_t hu = (int64_t)1 << (J - lev);
+            const double h = P->dt * ldexp(1.0, -lev);
+            const double A0 = drive_sub(P, n, u, J), A1 = drive_sub(P, n, u + hu, J);
+            double e = 0.0;
+            for (uint64_t i = 0; i < count; ++i) {
+                or_path *s = &st[i];
+                double dxi = 0.0;
+                if (P->noise & OR_GAUSS)
+                    dxi = (double)or_three_point(P, first_path + i, (int64_t)s->kA) * G * sqrt(3.0 * h);
+                predictor_corrector(P, &s->x, &s->v, h, dxi, 0.0, c[i], 0.0, A0, A1, &chi[i]);
+                s->kA += 1;
+                if (chi[i] > e || chi[i] != chi[i]) e = chi[i] != chi[i] ? INFINITY : chi[i];
+            }
+            u += hu;
+            int next = lev;
+            if (e > P->step_tol) {
+                if (lev < J) next = lev + 1;
+            } else if (e < P->step_tol / 16.0 && lev > 0 && u % (2 * hu) == 0) {
+                next = lev - 1;
+            }
+            for (uint64_t i = 0; i < count; ++i) st[i].lev = next;
+        }
+        for (uint64_t i = 0; i < count; ++i) {
+            if (P->dyn == OR_INERTIAL) st[i].v += z[i];
+            else st[i].x += z[i];
+            fold(P, &st[i]);
+            if (n + 1 == P->n_window) { st[i].xi = st[i].x; st[i].wi = st[i].w; }
+        }
+    }
+}
+
+/* Advance paths first_path .. first_path + count - 1 of an ensemble of n_paths
+ * with step control from step n_from to n_to (in units of dt).  first_path must
+ * start a group (a multiple of 64), and the paths must cover whole groups (count a
+ * multiple of 64, or reaching n_paths).  Returns 0, or -1 for a misaligned range. */
+int or_advance_adaptive(const or_params *P, uint64_t first_path, uint64_t count, uint64_t n_paths,
+                        int64_t n_from, int64_t n_to, or_path *st)
+{
+    if (first_path % 64 != 0 || first_path + count > n_paths) return -1;
+    if (count % 64 != 0 && first_path + count != n_paths) return -1;
+    if (P->max_halvings < 0 || P->max_halvings > 20) return -1;
+    if (P->noise & (OR_NORMAL | OR_JUMP_GRID)) return -1;
+    for (uint64_t g = 0; g < count; g += 64) {
+        uint64_t c = count - g < 64 ? count - g : 64;
+        advance_group(P, first_path + g, c, n_from, n_to, st + g);
+    }
+    return 0;
 }
 
 /* eq. (31): per-path velocity ((x(t_f) - x(t_i)) / (t_f - t_i)), t_f = n_now dt. */

@@ -372,7 +372,7 @@ def test_stratonovich_tilted_washboard(orc, pot, F, D):
 @pytest.mark.parametrize("a,DP", [(1.5, 0.5), (2.5, 1.0)])
 def test_eq21a_poisson_tent(orc, a, DP):
     lam, zeta = a * a / DP, DP / a                  # a = lambda zeta, D_P = lambda zeta^2
-    dt = (1.0 / lam) / 400                          # spp = 400 per 1/lambda, as in Sec. 5
+    dt = (1.0 / lam) / 400                          # spp = 400 per 1/lambda, as in Sec. 6
     n = int(150 / lam / dt)
     P = orc.Params(pot=orc.POT_TENT, noise=orc.POISSON, lam=lam, zeta=zeta, dt=dt,
                    x0_lo=0.0, x0_hi=2.0, n_window=n // 10)
@@ -785,3 +785,152 @@ def test_inertial_kicks_act_on_velocity(orc):
     for mode, er in errs.items():
         assert er[0] / er[1] > 3.3 and er[1] / er[2] > 3.3, (mode, er)
         assert er[2] < 1e-4, (mode, er)
+
+
+# ---------------------------------------------------------------------------
+# Step-size control on chi = predictor - corrector (the paragraph after
+# Algorithm 1): steps dt / 2^j, one controller per group of 64 paths
+# ---------------------------------------------------------------------------
+def test_step_control_without_halvings_is_the_fixed_step_scheme(orc):
+    """max_halvings = 0 leaves only the step dt: every path equals the fixed-step
+    scheme bit for bit, for every noise the control supports."""
+    import dataclasses
+    for noise in (0, orc.GAUSS, orc.GAUSS | orc.POISSON, orc.GAUSS | orc.DICH, orc.POISSON | orc.DICH):
+        P = _c2_like(orc, noise=noise, Fa=0.5, Fb=1.0, mua=1.0, mub=2.0, n_window=150)
+        a = orc.run(P, 0, 130, 400)
+        b = orc.run(dataclasses.replace(P, step_tol=1e-9, max_halvings=0), 0, 130, 400)
+        for f in a.dtype.names:
+            if f != "kA":
+                assert np.array_equal(a[f], b[f]), (noise, f)
+        assert (b["kA"] == 400).all() and (b["lev"] == 0).all()
+
+
+def _pendulum(orc, spp, **kw):
+    return orc.Params(dyn=orc.INERTIAL, pot=orc.POT_SIN, noise=0, gamma=0.9, a=4.2, omega=4.9, F=0.1, spp=spp,
+                      x0_lo=0.3, x0_hi=0.3, v0_lo=0.5, v0_hi=0.5, **kw)
+
+
+def test_step_control_deterministic_error_and_step_count(orc):
+    """D = 0, the driven inertial pendulum over two drive periods against DOP853.
+    chi of a second-order scheme is a local error of order h^3, so holding it below tol
+    takes a number of steps growing as tol^(-1/3) (2.15x per decade of tol), and the
+    global error falls as tol falls.  A chi of another order (h^2: 3.2x per decade), a
+    drive taken at the wrong time inside a sub-step or a sub-step of the wrong length
+    breaks one of these."""
+    g, a, w, F = 0.9, 4.2, 4.9, 0.1
+    T = 2 * TWO_PI / w
+
+    def rhs(t, y):
+        return [y[1], -g * y[1] - TWO_PI * math.cos(TWO_PI * y[0]) + a * math.cos(w * t) + F]
+
+    ref = cf.solve_deterministic(rhs, [0.3, 0.5], T)
+    steps, errs = [], []
+    for tol in (1e-4, 1e-5, 1e-6, 1e-7):
+        P = _pendulum(orc, 25, step_tol=tol, max_halvings=8)
+        st = orc.run(P, 0, 1, 50)
+        assert st["lev"][0] <= 8
+        steps.append(int(st["kA"][0]))
+        errs.append(max(abs(orc.unwrapped(P, st)[0] - ref[0]), abs(st["v"][0] - ref[1])))
+    ratios = [b / a for a, b in zip(steps, steps[1:])]
+    assert all(1.8 < r < 2.6 for r in ratios), (steps, ratios)
+    assert all(e2 < e1 / 2 for e1, e2 in zip(errs, errs[1:])), errs
+    assert errs[-1] < 1e-4
+    # the fixed step of the same base dt is far worse than the controlled one
+    P0 = _pendulum(orc, 25)
+    st0 = orc.run(P0, 0, 1, 50)
+    e0 = max(abs(orc.unwrapped(P0, st0)[0] - ref[0]), abs(st0["v"][0] - ref[1]))
+    assert e0 > 50 * errs[-1]
+
+
+def test_step_control_overdamped_ratchet_deterministic(orc):
+    a, w, F = 0.8, 3.0, 0.3
+    T = 3 * TWO_PI / w
+
+    def rhs(t, y):
+        x = y[0]
+        return [TWO_PI * math.cos(TWO_PI * x) + math.pi * math.cos(2 * TWO_PI * x) + a * math.cos(w * t) + F]
+
+    ref = cf.solve_deterministic(rhs, [0.1], T)
+    errs = []
+    for tol in (1e-5, 1e-7, 1e-9):
+        P = orc.Params(pot=orc.POT_RATCHET, noise=0, a=a, omega=w, F=F, spp=30, x0_lo=0.1, x0_hi=0.1,
+                       step_tol=tol, max_halvings=10)
+        st = orc.run(P, 0, 1, 90)
+        errs.append(abs(orc.unwrapped(P, st)[0] - ref[0]))
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-6, errs
+
+
+def test_step_control_ou_moments(orc):
+    """Linear drift with Gaussian noise: each sub-step takes its own three-point draw
+    of variance G^2 h, so E x(T) and Var x(T) stay within sampling error plus the
+    coarsest step's bias of the continuum OU values x0 e^(-kT) and (D/k)(1 - e^(-2kT)).
+    Reusing a draw across sub-steps, or scaling a sub-step's draw with dt, would
+    multiply the variance."""
+    k, D, dt, n = 1.5, 0.4, 0.2, 20
+    P = orc.Params(pot=orc.POT_HARMONIC, k_harm=k, noise=orc.GAUSS, D=D, dt=dt, x0_lo=1.0, x0_hi=1.0,
+                   step_tol=2e-3, max_halvings=4, seed=17)
+    N = 1 << 15
+    st = orc.run(P, 0, N, n, threads=THREADS)
+    steps_per_dt = st["kA"].mean() / n
+    assert 2.0 < steps_per_dt < 16.0                   # the control is active
+    x = st["x"]
+    T = n * dt
+    mean_c, var_c = math.exp(-k * T), D / k * (1.0 - math.exp(-2 * k * T))
+    # coarsest step dt: the discrete mean R^n and variance (exact for the fixed step)
+    m_coarse, v_coarse = cf.ou_discrete_moments(1.0, k, math.sqrt(2 * D), dt, n)
+    se_m, se_v = math.sqrt(var_c / N), var_c * math.sqrt(2.0 / N)
+    assert abs(x.mean() - mean_c) <= 4 * se_m + abs(m_coarse - mean_c)
+    assert abs(x.var() - var_c) <= 4 * se_v + abs(v_coarse - var_c)
+    assert abs(x.var() - var_c) < 0.05 * var_c
+
+
+def test_step_control_kicks_and_flips_stay_on_the_dt_grid(orc):
+    """The jump processes keep their fixed-grid times under step control: an inertial
+    free particle with drive and Poisson kicks matches the exact solution with the kick
+    of step n at t_{n+1}; an overdamped free particle with dichotomous noise moves by
+    exactly dt times the sum of its levels (the sub-steps of a step add up to dt)."""
+    errs = []
+    for tol in (1e-4, 1e-6):
+        P = orc.Params(dyn=orc.INERTIAL, pot=orc.POT_FREE, noise=orc.POISSON, gamma=0.8, lam=2.5, zeta=0.6,
+                       a=1.5, omega=3.0, F=0.2, spp=25, seed=33, x0_lo=0.0, x0_hi=1.0, v0_lo=-1.0, v0_hi=1.0,
+                       step_tol=tol, max_halvings=8)
+        n, dt = 100, P.step()
+        st0 = orc.init(P, 0, 64)
+        x0 = orc.unwrapped(P, st0)
+        st = orc.advance_adaptive(P, st0.copy(), 0, 64, 0, n)
+        xT = orc.unwrapped(P, st)
+        e = []
+        for p in range(64):
+            kicks = [((m + 1) * dt, z) for m, z in _fixed_grid_kick_steps(orc, P, p, n)]
+            assert st["kP"][p] == len(kicks)
+            xe, ve = _inertial_free_exact(P, x0[p], st0["v"][p], n * dt, kicks)
+            e.append(max(abs(xT[p] - xe), abs(st["v"][p] - ve)))
+        errs.append(max(e))
+    assert errs[1] < errs[0] / 5 and errs[1] < 1e-4, errs
+    P = orc.Params(pot=orc.POT_FREE, noise=orc.DICH, Fa=0.7, Fb=1.3, mua=3.0, mub=2.0, dt=0.01, seed=3,
+                   step_tol=1e-6, max_halvings=3)
+    st0 = orc.init(P, 0, 64)
+    x0 = orc.unwrapped(P, st0)
+    st = orc.advance_adaptive(P, st0.copy(), 0, 64, 0, 300)
+    ref = orc.advance(P.__class__(**{**P.__dict__, "step_tol": 0.0, "max_halvings": 0}),
+                      orc.init(P, 0, 64), 0, 0, 300)
+    assert np.array_equal(st["mD"], ref["mD"]) and np.array_equal(st["d"], ref["d"])
+    assert np.allclose(orc.unwrapped(P, st) - x0, orc.unwrapped(P, ref) - x0, rtol=0, atol=1e-12)
+
+
+def test_step_control_groups_and_chunks(orc):
+    """A path depends only on the paths of its group of 64; any split of the horizon
+    into calls gives the same bits."""
+    P = _c2_like(orc, noise=orc.GAUSS, D=0.01, step_tol=3e-5, max_halvings=5, n_window=100)
+    a = orc.run(P, 0, 200, 300, n_paths=200)                 # groups 0-63, 64-127, 128-191, 192-199
+    b = orc.run(P, 64, 64, 300, n_paths=200)
+    assert a[64:128].tobytes() == b.tobytes()
+    c = orc.run(P, 192, 8, 300, n_paths=200)
+    assert a[192:].tobytes() == c.tobytes()
+    d = orc.init(P, 0, 200)
+    orc.advance_adaptive(P, d, 0, 200, 0, 77)
+    orc.advance_adaptive(P, d, 0, 200, 77, 300)
+    assert a.tobytes() == d.tobytes()
+    assert len(set(a["lev"][:64])) == 1 and a["kA"][0] > 300
+    with pytest.raises(ValueError):
+        orc.advance_adaptive(P, orc.init(P, 10, 64), 10, 200, 0, 5)
