@@ -129,28 +129,150 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def oracle_baseline(w, seconds: float, threads: int):
-    """Time the FP64 oracle on paths 0..S-1 of the workload (full horizon), S sized
-    from a short pilot so that the run takes about `seconds`."""
+ORACLE_SUBSET = 4096
+
+
+def host_threads() -> int:
+    """Host threads this process may run on (its CPU affinity set)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
+
+
+def oracle_baseline(w, seconds: float | None, threads: int):
+    """Time the FP64 oracle on paths 0..S-1 of the workload over its full horizon:
+    S = the 4096-path comparison subset (seconds None), or S sized from a short pilot
+    so that the run takes about `seconds`."""
     import oracle
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from helpers import to_oracle
     oracle.build(force=False)
     P = to_oracle(w)
-    pilot_paths, pilot_steps = 4 * threads, min(2000, w.n_steps)
-    t = time.perf_counter()
-    oracle.run(P, 0, pilot_paths, pilot_steps, threads=threads)
-    rate = pilot_paths * pilot_steps / (time.perf_counter() - t)
-    S = int(rate * seconds / w.n_steps) // threads * threads
-    S = max(threads, min(S, 4096, w.n_paths))
+    if seconds is None:
+        S = min(ORACLE_SUBSET, w.n_paths)
+    else:
+        pilot_paths, pilot_steps = 4 * threads, min(2000, w.n_steps)
+        t = time.perf_counter()
+        oracle.run(P, 0, pilot_paths, pilot_steps, threads=threads)
+        rate = pilot_paths * pilot_steps / (time.perf_counter() - t)
+        S = int(rate * seconds / w.n_steps) // threads * threads
+        S = max(threads, min(S, ORACLE_SUBSET, w.n_paths))
     t = time.perf_counter()
     st = oracle.run(P, 0, S, w.n_steps, threads=threads)
     el = time.perf_counter() - t
-    s = oracle.stats(oracle.velocity(P, st, w.n_steps))
+    vp = oracle.velocity(P, st, w.n_steps)
+    s = oracle.stats(vp)
     return dict(value=S * w.n_steps / el, unit="path-steps/s", cores=threads, kind="oracle",
                 sample="paths 0..%d of the workload over its full %d-step horizon (%.3g path-steps, %.1f s)"
                        % (S - 1, w.n_steps, S * w.n_steps, el),
-                mean_v=s.mean, se=s.se, n_paths=S)
+                mean_v=s.mean, se=s.se, n_paths=S, vp=vp)
+
+
+def oracle_check(gpu_vp, gpu_stats, ob):
+    """<v> of the GPU against the FP64 oracle on the same paths (same random streams):
+    unpaired (subset means), paired (per-path differences) and full ensemble against the
+    oracle subset, each at 3 standard errors."""
+    import numpy as np
+    import oracle
+    S = ob["n_paths"]
+    g = oracle.stats(gpu_vp[:S])
+    d = oracle.stats(gpu_vp[:S] - ob["vp"])
+    return {"oracle_paths": S, "oracle_mean_v": ob["mean_v"], "oracle_se_v": ob["se"],
+            "gpu_subset_mean_v": g.mean, "gpu_subset_se_v": g.se,
+            "paired_mean_diff": d.mean, "paired_se": d.se,
+            "unpaired_within_3se": abs(g.mean - ob["mean_v"]) <= 3 * math.hypot(g.se, ob["se"]),
+            "paired_within_3se": abs(d.mean) <= 3 * d.se + 1e-12,
+            "ensemble_within_3se": abs(gpu_stats.mean - ob["mean_v"]) <= 3 * math.hypot(gpu_stats.se, ob["se"]),
+            "paths_within_1e-3": float(np.mean(np.abs(gpu_vp[:S] - ob["vp"])
+                                               <= 1e-3 * np.maximum(1.0, np.abs(ob["vp"]))))}
+
+
+def time_ensemble(w, steps: int, warmup: int, tune=None):
+    """Run `warmup` + `steps` passes of the hot path (create with initial conditions,
+    integrate the horizon, reduce eq. 31) on torch's current stream.  Returns (wall
+    seconds of the timed passes, integration seconds per pass from HIP events on that
+    stream, bm_stats of the last pass, per-path velocities of paths 0..4095)."""
+    import torch
+    from paper_1409_4923_amd import bmotor as B
+    from paper_1409_4923_amd import workloads as W
+    dev = torch.device("cuda:0")
+    m, r = W.to_c(w)
+    ws_bytes = B.bm_ensemble_workspace_size(m, r)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    out = torch.empty(B.STATS_BYTES, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    n_sub = min(ORACLE_SUBSET, w.n_paths)
+    vp = torch.empty(n_sub, dtype=torch.float64, device=dev)
+    events = []
+
+    def one_pass(timed: bool, last: bool):
+        h = B.bm_ensemble_create(m, r, ws.data_ptr(), ws_bytes, stream.cuda_stream)
+        try:
+            if tune is not None:
+                B.bm_ensemble_set_tune(h, tune)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            B.bm_integrate(h, w.n_steps)
+            e1.record(stream)
+            B.bm_reduce(h, out.data_ptr())
+            if last:
+                B.bm_read_paths(h, 0, n_sub, None, None, None, vp.data_ptr())
+        finally:
+            B.bm_ensemble_destroy(h)
+        if timed:
+            events.append((e0, e1))
+
+    for i in range(warmup):
+        one_pass(False, False)
+        print("%s: warmup pass %d done" % (w.name, i), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        one_pass(True, False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    print("%s: timed %d passes in %.3f s" % (w.name, steps, wall), file=sys.stderr, flush=True)
+    int_s = sum(a.elapsed_time(b) for a, b in events) / 1e3 / steps
+    one_pass(False, True)          # untimed: the per-path velocities for the oracle comparison
+    torch.cuda.synchronize()
+    st = B.stats_from_bytes(out.cpu().numpy().tobytes())
+    return wall, int_s, st, vp.cpu().numpy()
+
+
+def roofline_of(w, int_s: float):
+    from paper_1409_4923_amd import workloads as W
+    ops, trans, flops = algorithmic_work(w)
+    ps = w.path_steps()
+    launches = 2 if 0 < w.n_window < w.n_steps else 1
+    peak_flops = FP32_PEAK_FLOPS if w.prec == W.F32 else FP64_PEAK_FLOPS
+    achieved = ops * ps / int_s
+    return {"bound": "alu", "kernel": "k_advance (integration loop)",
+            "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "TOP/s (VALU lane-ops)",
+            "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": None,
+            "ops_per_path_step": ops, "trans_ops_per_path_step": trans,
+            "path_steps_per_launch": ps / launches, "kernel_ms_per_launch": int_s * 1e3 / launches,
+            "launches_per_step": launches,
+            "fp32_flops" if w.prec == W.F32 else "fp64_flops": {
+                "flops_per_path_step": flops, "achieved_tflops": flops * ps / int_s / 1e12,
+                "peak_tflops": peak_flops / 1e12, "frac": flops * ps / int_s / peak_flops}}
+
+
+def ensemble_leg(w, steps: int, warmup: int, threads: int, with_oracle: bool):
+    """A timed pass of another workload: path-steps/s, the roofline of its
+    integration kernel and its <v> against the FP64 oracle on paths 0..4095."""
+    wall, int_s, st, vp = time_ensemble(w, steps, warmup)
+    res = {"workload": w.name, "n_paths": w.n_paths, "n_steps": w.n_steps, "n_window": w.n_window,
+           "noise_mask": w.noise, "dtype": "f32" if w.prec == 1 else "f64", "steps": steps,
+           "path_steps_per_s": w.path_steps() * steps / wall, "ms_per_step": 1e3 * wall / steps,
+           "mean_v": st.mean, "se_v": st.se, "n_nonfinite": st.n_nonfinite, "roofline": roofline_of(w, int_s)}
+    if with_oracle:
+        ob = oracle_baseline(w, None, threads)
+        res["oracle"] = oracle_check(vp, st, ob)
+        res["oracle"]["path_steps_per_s"] = ob["value"]
+        res["oracle"]["cores"] = threads
+    return res
 
 
 def host_cpu_model() -> str:
@@ -397,8 +519,8 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="scan,scheme,infer,surrogate",
-                    help="extra legs: scan, scheme, infer, surrogate (or none)")
+    ap.add_argument("--legs", default="c3,c2jump,scan,scheme,infer,surrogate",
+                    help="extra legs: c3, c2jump, scan, scheme, infer, surrogate (or none)")
     ap.add_argument("--labels", type=int, default=200_000)
     ap.add_argument("--label-paths", type=int, default=256)
     ap.add_argument("--label-periods", type=int, default=100)
@@ -414,13 +536,13 @@ def main():
     args = ap.parse_args()
     if args.calibrate_valu:
         import torch
-        from paper_1409_4923_amd import bmotor as B
+        from paper_1409_4923_amd import probe as PR
         n = 256 * 32 * 256                        # 32 work-groups of 256 lanes per CU
         out = torch.empty(n, dtype=torch.float32, device="cuda")
         stream = torch.cuda.current_stream().cuda_stream
         rec = {"peak_lane_ops_per_s": VALU_LANE_OPS_PEAK}
         for mix, name in ((0, "fma"), (1, "fma_cmp_select")):
-            r = B.bm_valu_probe(mix, 20000, out.data_ptr(), n, stream)
+            r = PR.valu_probe(mix, 20000, out.data_ptr(), n, stream)
             rec[name] = {"lane_ops_per_s": r, "frac_of_peak": r / VALU_LANE_OPS_PEAK}
         print(json.dumps({"valu_probe": rec}), flush=True)
         return
@@ -444,55 +566,13 @@ def main():
     from paper_1409_4923_amd import workloads as W
 
     w = {"c1": W.C1, "c2": W.C2, "c3": W.C3}[args.config]
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    m, r = W.to_c(w)
-    ws_bytes = B.bm_ensemble_workspace_size(m, r)
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    out = torch.empty(B.STATS_BYTES, dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream(dev)
+    torch.cuda.set_device(torch.device("cuda:0"))
     tune = B.make_tune(args.ppl, args.block) if args.ppl else None
-
-    kernel_ms = []
-
-    def one_step(timed: bool):
-        h = B.bm_ensemble_create(m, r, ws.data_ptr(), ws_bytes, stream.cuda_stream)
-        try:
-            if tune is not None:
-                B.bm_ensemble_set_tune(h, tune)
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            B.bm_integrate(h, w.n_steps)
-            e1.record(stream)
-            B.bm_reduce(h, out.data_ptr())
-        finally:
-            B.bm_ensemble_destroy(h)
-        if timed:
-            kernel_ms.append((e0, e1))
-
-    for i in range(args.warmup):
-        one_step(False)
-        print("warmup step %d done" % i, file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        one_step(True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    print("timed %d steps in %.3f s" % (args.steps, t1 - t0), file=sys.stderr, flush=True)
-
-    st = B.stats_from_bytes(out.cpu().numpy().tobytes())
-    int_s = sum(a.elapsed_time(b) for a, b in kernel_ms) / 1e3 / args.steps
-    launches = 2 if 0 < w.n_window < w.n_steps else 1
-    ps_per_step = w.path_steps()
-    value = ps_per_step * args.steps / (t1 - t0)
-    ops, trans, flops = algorithmic_work(w)
-    achieved = ops * ps_per_step / int_s
-    traffic = None
+    wall, int_s, st, vp = time_ensemble(w, args.steps, args.warmup, tune)
+    value = w.path_steps() * args.steps / wall
+    roof = roofline_of(w, int_s)
     if w.name == TRAFFIC_WORKLOAD and kernel_sources_sha256() == KERNEL_SOURCES_SHA256:
-        traffic = TRAFFIC_BYTES_PER_LAUNCH
-    peak_flops = FP32_PEAK_FLOPS if w.prec == W.F32 else FP64_PEAK_FLOPS
+        roof["traffic"] = TRAFFIC_BYTES_PER_LAUNCH
     rec = {
         "metric": "path-steps/s",
         "value": value,
@@ -500,7 +580,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * (t1 - t0) / args.steps,
+        "ms_per_step": 1e3 * wall / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -510,47 +590,39 @@ def main():
                    "n_window": w.n_window, "dt": w.step(), "noise_mask": w.noise,
                    "parallelism": "single-gpu", "paths_per_lane": args.ppl or 1, "block": args.block},
         "mean_v": st.mean, "se_v": st.se, "n_nonfinite": st.n_nonfinite,
-        "roofline": {
-            "bound": "alu",
-            "kernel": "k_advance (integration loop)",
-            "achieved": achieved / 1e12,
-            "peak": VALU_LANE_OPS_PEAK / 1e12,
-            "unit": "TOP/s (VALU lane-ops)",
-            "frac": achieved / VALU_LANE_OPS_PEAK,
-            "traffic": traffic,
-            "ops_per_path_step": ops,
-            "trans_ops_per_path_step": trans,
-            "path_steps_per_launch": ps_per_step / launches,
-            "kernel_ms_per_launch": int_s * 1e3 / launches,
-            "launches_per_step": launches,
-            "fp32_flops": {"achieved_tflops": flops * ps_per_step / int_s / 1e12,
-                           "peak_tflops": peak_flops / 1e12,
-                           "frac": flops * ps_per_step / int_s / peak_flops},
-        },
+        "roofline": roof,
         "cpu_baseline": None,
     }
+    threads = host_threads()
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        cb = oracle_baseline(w, args.cpu_seconds, threads)
+        # the oracle on the 4096-path comparison subset, on every host thread this
+        # process may use, timed in the same run
+        cb = oracle_baseline(w, None, threads)
         rec["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
-        rec["oracle_mean_v"] = cb["mean_v"]
-        rec["oracle_se_v"] = cb["se"]
-        rec["mean_v_within_3se"] = abs(st.mean - cb["mean_v"]) <= 3 * math.hypot(st.se, cb["se"])
+        rec["cpu_baseline"]["host_cpus"] = os.cpu_count()
+        rec["cpu_baseline"]["host_cpu"] = host_cpu_model()
+        rec["oracle"] = oracle_check(vp, st, cb)
+        rec["mean_v_within_3se"] = rec["oracle"]["ensemble_within_3se"]
         rec["speedup_vs_oracle"] = value / cb["value"]
         # the paper's GPU/CPU figure is against one CPU core
-        one = oracle_baseline(w, args.cpu_seconds / 4, 1)
+        one = oracle_baseline(w, args.cpu_seconds / 2, 1)
         rec["cpu_baseline"]["single_core"] = {"value": one["value"], "sample": one["sample"]}
-        rec["cpu_baseline"]["host_cpu"] = host_cpu_model()
         rec["speedup_vs_one_core"] = value / one["value"]
         # the same workload with FP64 paths, against the same (FP64) oracle core
         f64 = fp64_rate(w)
         rec["fp64_paths"] = {"path_steps_per_s": f64, "speedup_vs_one_core": f64 / one["value"],
                              "sample": "all %d paths, %d steps" % (w.n_paths, FP64_SAMPLE_STEPS)}
-        # the paper's figures (Sec. 6): GPU over the same program on one CPU core
+        # the paper's figures (Sec. 7): GPU over the same program on one CPU core
         rec["paper_speedup"] = {"fp32": 3000, "fp64": [700, 400],
                                 "hardware": "NVIDIA GeForce GTX TITAN Black vs one core of an "
                                             "Intel Core i7-3930K at 3.2 GHz"}
     legs = [l for l in args.legs.split(",") if l and l != "none"]
+    if "c3" in legs and w.name != W.C3.name:
+        rec["c3"] = ensemble_leg(W.C3, 2, 1, threads, not args.no_cpu_baseline)
+    if "c2jump" in legs:
+        rec["c2_jump_adapted_grid"] = ensemble_leg(W.C2.with_(name="inertial-poisson-jump-grid-f32-2^20",
+                                                              noise=W.GAUSS | W.POISSON | W.JUMP_GRID),
+                                                   2, 1, threads, not args.no_cpu_baseline)
     if "scan" in legs:
         rec["scan"] = scan_leg(args)
     if "scheme" in legs:

@@ -9,10 +9,11 @@
  *   - Algorithm 1: weak order 2.0 predictor-corrector step, three drift
  *     evaluations per step;
  *   - Algorithm 2 / eq. (25): simplified three-point Gaussian increment;
- *   - Algorithm 3 / eqs. (3)-(8), (26)-(27): white Poissonian increment on the
- *     jump-adapted grid;
+ *   - Algorithm 3 / eqs. (3)-(8), (26)-(27): white Poissonian increment, by
+ *     default with the kicks on the fixed step grid (the integer countdown of the
+ *     algorithm); BM_NOISE_JUMP_GRID puts them at their exact times;
  *   - Algorithm 4 / eqs. (13)-(17), (29)-(30): dichotomous increment;
- *   - Sec. 4 (Instruction optimization): x kept modulo L, periods counted apart;
+ *   - Sec. 5 (Instruction optimization): x kept modulo L, periods counted apart;
  *   - eq. (31): <v> = < (x(t_f) - x(t_i)) / (t_f - t_i) > over the ensemble.
  *
  * Conventions shared by every entry point
@@ -47,7 +48,7 @@
 extern "C" {
 #endif
 
-#define BM_ABI_VERSION 1u
+#define BM_ABI_VERSION 2u
 
 /* return codes */
 #define BM_OK               0
@@ -72,12 +73,12 @@ extern "C" {
 #define BM_NOISE_POISSON 2u  /* eta: white Poissonian noise, Algorithm 3                    */
 #define BM_NOISE_DICH    4u  /* Gamma: dichotomous noise, Algorithm 4                       */
 /* xi integrated with normal increments N(0, G^2 dt) instead of eq. (25)'s three-point
- * law: the non-simplified scheme, for comparison (Sec. 3).  The standard normal of
+ * law: the non-simplified scheme, for comparison (Sec. 4).  The standard normal of
  * step n is the Box-Muller transform of words (2j, 2j+1), j = (n mod 4)/2, of the
  * Philox block (n/4, path, point, tag 0): cos for even n, sin for odd n.  Excludes
  * BM_NOISE_GAUSS; ensembles only (bm_scan rejects it with BM_ERR_UNSUPPORTED). */
 #define BM_NOISE_NORMAL  8u
-/* With BM_NOISE_POISSON: the jump-adapted grid of Sec. 3 (kicks at their exact
+/* With BM_NOISE_POISSON: the jump-adapted grid of Sec. 4 (kicks at their exact
  * times t_i; waiting times E/lambda are not rounded to the step).  A step that holds
  * kicks is cut at each t_i; each piece is integrated by Algorithm 1 with its own
  * length and a Gaussian increment of matching variance (the step's own draw scaled
@@ -122,7 +123,29 @@ typedef struct bm_run {
     uint64_t seed;             /* Philox key                                                */
     double x0_lo, x0_hi;       /* x(0) ~ U[x0_lo, x0_hi)                                    */
     double v0_lo, v0_hi;       /* v(0) ~ U[v0_lo, v0_hi) (inertial)                         */
+    double step_tol;           /* step-size control on chi (see below); 0: fixed step dt    */
+    uint32_t max_halvings;     /* with step_tol > 0: smallest step dt / 2^max_halvings, 1..8 */
+    uint32_t pad;              /* 0                                                         */
 } bm_run;
+
+/* Step-size control.  The paper notes after Algorithm 1 that chi = (predictor) -
+ * (corrector) estimates the local error and may steer the step size; it gives no
+ * controller.  This library's: steps are dt / 2^l, 0 <= l <= max_halvings, starting
+ * at the smallest; one controller serves each group of 64 consecutive paths
+ * (64 g .. 64 g + 63, those below n_paths) -- one wavefront of the kernel.  After
+ * each step, if some path of the group has max(|chi_x|, |chi_v|) > step_tol (or a
+ * NaN) the next step is halved; if all have it below step_tol / 16 it is doubled,
+ * where the doubled step starts on its own grid (so no step crosses a multiple of
+ * dt); otherwise it is kept.  Every step is accepted.  Step k of a path (counting
+ * steps of every size) takes the k-th Algorithm 2 draw of its tag-0 stream scaled
+ * by G sqrt(3 h).  The drive at t = (n + u / 2^L) dt is a cos(2 pi ((n mod spp)
+ * 2^L + u) / (spp 2^L)) + F, L = max_halvings.  The Poisson and dichotomous
+ * processes keep their dt grid: a flip at step n sets the level of the whole step,
+ * a kick drawn at step n is added after its last sub-step.  A path's result depends
+ * on the paths of its group (not on the launch shape or chunking).  n_steps and
+ * window_start still count steps of dt.  Ensembles only (bm_scan rejects it); not
+ * with BM_NOISE_NORMAL or BM_NOISE_JUMP_GRID (BM_ERR_UNSUPPORTED); one path per
+ * lane. */
 
 typedef struct bm_stats {
     uint64_t n;            /* paths with a finite velocity                                */
@@ -201,14 +224,50 @@ int bm_ensemble_steps(const bm_ensemble *e, uint64_t *n_done);
  * device pointer d_out.  BM_ERR_STATE unless steps done > window_start. */
 int bm_reduce(bm_ensemble *e, bm_stats *d_out);
 
+/* The whole state of one path, lossless: what Algorithm 5 of the paper loads into
+ * registers before a kernel call and saves after it (position kept modulo L as in
+ * "Instruction optimization", the noise countdowns of Algorithms 3 and 4, the
+ * eq. (31) window snapshot).  Values are widened to FP64 / int64 on export, so a
+ * record read from an ensemble and written back reproduces its state bit for bit. */
+typedef struct bm_path {
+    int64_t periods;         /* w: periods folded away; unwrapped position = periods L + x */
+    double x;                /* folded position (within a couple of periods of [0, L))  */
+    double v;                /* velocity (inertial; 0 for overdamped paths)             */
+    int64_t periods_window;  /* w and x at the window start t_i of eq. (31)             */
+    double x_window;
+    double kick_frac;        /* jump-adapted grid: fraction of its step at which the
+                                next kick falls (0 otherwise)                          */
+    int64_t noise[5];        /* Poisson countdown, Poisson kicks so far, dichotomous
+                                countdown, dichotomous flips so far, dichotomous state
+                                (0: -Fa, 1: +Fb); 0 for absent noises                  */
+    int64_t step_level;      /* step control: the next step is dt / 2^step_level       */
+    int64_t steps_taken;     /* step control: steps taken (all sizes); 0 otherwise     */
+} bm_path;
+
 /* Enqueue a copy of paths [first, first + count) to device arrays (any may be
  * NULL): d_x unwrapped position w L + x (FP64), d_v velocity (FP64),
- * d_noise 5 x int64 per path: Poisson countdown, Poisson kicks so far,
- * dichotomous countdown, dichotomous flips so far, dichotomous state (0: -Fa,
- * 1: +Fb).  d_vp (FP64) receives the eq. (31) per-path velocity once
- * steps done > window_start (else it is left untouched). */
+ * d_noise 5 x int64 per path (the layout of bm_path.noise), d_vp (FP64) the
+ * eq. (31) per-path velocity once steps done > window_start (else it is left
+ * untouched), d_state one bm_path record per path (8-byte aligned). */
 int bm_read_paths(bm_ensemble *e, uint64_t first, uint64_t count,
-                  double *d_x, double *d_v, int64_t *d_noise, double *d_vp);
+                  double *d_x, double *d_v, int64_t *d_noise, double *d_vp, bm_path *d_state);
+
+/* Inverse of bm_read_paths: enqueue a copy of the records d_state [count] (device,
+ * 8-byte aligned) into paths [first, first + count), interpreted as their state
+ * after the steps the ensemble has done (bm_ensemble_steps).  Stored in the path
+ * precision (FP32 rounds; a record read from an FP32 ensemble round-trips
+ * exactly).  The window snapshot is taken from the record when steps done >
+ * window_start, set to the written position when steps done == window_start, and
+ * left to the integration otherwise.  Only the noise fields of the model's noises
+ * are used.  Values outside their ranges are clamped on the device (periods to
+ * int32, countdowns to [0, 2^31 - 1], counts to [0, 2^32 - 1], state to 0/1,
+ * kick_frac outside [0, 1) or NaN to 0, step_level to [0, max_halvings], steps_taken
+ * to [0, 2^32 - 1]): a bad record gives a wrong path, never a fault.  Under step
+ * control the records of a group of 64 paths must share step_level and steps_taken
+ * (as exported); the kernel takes the group's values from its first path.  To resume exported states in a fresh workspace, open it with
+ * bm_ensemble_attach (steps_done = the exporter's) and write every path; writing
+ * at step 0 after bm_ensemble_create sets arbitrary initial conditions. */
+int bm_write_paths(bm_ensemble *e, uint64_t first, uint64_t count, const bm_path *d_state);
 
 /* eq. (19): add a histogram of the current folded positions y = x mod L of all
  * paths to d_counts (n_bins uint64 counters, device; the caller zeroes them):
@@ -218,7 +277,7 @@ int bm_read_paths(bm_ensemble *e, uint64_t first, uint64_t count,
 int bm_density(bm_ensemble *e, uint32_t n_bins, uint64_t *d_counts);
 
 /* ------------------------------------------------------------------------- */
-/* Batched parameter scan (Sec. 4, Execution configuration optimizations: the  */
+/* Batched parameter scan (Sec. 5, Execution configuration optimizations: the  */
 /* stochastic dynamics solved for many parameter values in one kernel call).   */
 /* ------------------------------------------------------------------------- */
 typedef struct bm_scan_plan bm_scan_plan;
@@ -269,6 +328,27 @@ int bm_scan_autotune(const bm_model *models, const bm_run *runs, size_t n_points
 int bm_tune_set_default(uint32_t dyn, uint32_t pot, uint32_t noise, uint32_t prec, const bm_tune *tune);
 int bm_tune_get_default(uint32_t dyn, uint32_t pot, uint32_t noise, uint32_t prec, bm_tune *out);
 
+/* The shape installed for this key by bm_tune_set_default, bm_scan_autotune or
+ * bm_tune_load: BM_OK and *out, or BM_ERR_STATE (with the built-in default in *out)
+ * when none is installed. */
+int bm_tune_lookup(uint32_t dyn, uint32_t pot, uint32_t noise, uint32_t prec, bm_tune *out);
+
+/* Persistent tuning cache (the "ideal number of particles" of the paper's
+ * performance section depends on the device: a tuned shape is kept per device).
+ * bm_tune_save writes every installed shape, with the architecture name and CU
+ * count of the device it was installed on, to the JSON file `path` (a temporary
+ * file renamed over it):
+ *   {"format": "libbmotor-tune", "version": 1, "entries": [
+ *     {"arch": "gfx950", "cus": 256, "dyn": 1, "pot": 0, "noise": 1, "prec": 1,
+ *      "paths_per_lane": 2, "block": 128, "groups_per_cu": 0}, ...]}
+ * bm_tune_load installs the entries of such a file whose arch and CU count match
+ * the current device (others are skipped; each entry is checked like
+ * bm_tune_set_default) and writes their number to *n_loaded (may be NULL).
+ * BM_ERR_INVALID_ARG for an unreadable or malformed file (nothing installed),
+ * BM_ERR_DEVICE without a gfx950 device. */
+int bm_tune_save(const char *path);
+int bm_tune_load(const char *path, uint32_t *n_loaded);
+
 /* ------------------------------------------------------------------------- */
 /* Learned surrogate of <v>(a, omega, F, D, gamma): an ensemble of MLPs         */
 /* 5 -> 256 -> 256 -> 256 -> 1 with tanh-GELU (Hendrycks & Gimpel), BF16       */
@@ -284,7 +364,7 @@ int bm_tune_get_default(uint32_t dyn, uint32_t pot, uint32_t noise, uint32_t pre
 /* W1[256][5] b1[256] W2[256][256] b2[256] W3[256][256] b3[256] W4[256] b4     */
 /* (row-major [out][in]).  BF16 weight copies: d_wbf [n_members][BM_MLP_BF16]  */
 /* = W1 | W2 | W3 | W4 (round to nearest even), refreshed by bm_mlp_cast and   */
-/* bm_mlp_adam.                                                                 */
+/* bm_mlp_adam_step.                                                            */
 /* ------------------------------------------------------------------------- */
 #define BM_MLP_INPUTS 5
 #define BM_MLP_HIDDEN 256
@@ -315,10 +395,10 @@ int bm_mlp_backward(uint32_t n_members, const float *d_params, const uint16_t *d
                     const float *d_t, const uint32_t *d_idx, uint64_t batch, float *d_grad, float *d_loss,
                     void *d_ws, size_t ws_bytes, void *stream);
 
-/* One Adam step (step counts from 1; bias-corrected moments d_m, d_v, FP32) on
- * d_params, followed by the BF16 copies in d_wbf. */
-int bm_mlp_adam(uint32_t n_members, float *d_params, const float *d_grad, float *d_m, float *d_v, uint16_t *d_wbf,
-                uint32_t step, float lr, float beta1, float beta2, float eps, void *stream);
+/* One Adam step (Kingma & Ba; step counts from 1; bias-corrected moments d_m,
+ * d_v, FP32) on d_params, followed by the BF16 copies in d_wbf. */
+int bm_mlp_adam_step(uint32_t n_members, float *d_params, const float *d_grad, float *d_m, float *d_v,
+                     uint16_t *d_wbf, uint32_t step, float lr, float beta1, float beta2, float eps, void *stream);
 
 /* Ensemble query: d_mean / d_std [batch] = mean and population standard
  * deviation of the members' predictions; the rows with std > threshold (or a
@@ -327,19 +407,6 @@ int bm_mlp_adam(uint32_t n_members, float *d_params, const float *d_grad, float 
 int bm_surrogate_query(uint32_t n_members, const float *d_params, const uint16_t *d_wbf, const float *d_x,
                        uint64_t batch, float threshold, float *d_mean, float *d_std, uint32_t *d_fallback_idx,
                        uint32_t *d_fallback_count, void *d_ws, size_t ws_bytes, void *stream);
-
-/* ---------------------------------------------------------------------------
- * Diagnostic (not part of the method): vector-ALU issue rate of the device, the
- * measured counterpart of the path kernels' roofline peak (one wave64 instruction
- * per CU per clock).  Runs n_out / 256 work-groups of 256 lanes, each lane
- * carrying eight independent non-packed FP32 FMA chains for `iters` iterations
- * (mix 0), or each FMA followed by a compare and a select (mix 1); d_out [n_out]
- * (device, caller-owned) receives one float per lane.  One warm-up launch, then
- * the best of three timed launches on `stream`; *lane_ops_per_s = lanes x iters x
- * 8 x (1 or 3) / time.  Synchronises `stream`.  n_out must be a multiple of 256
- * in [256, 2^28], iters in [1, 2^24]; otherwise BM_ERR_INVALID_ARG. */
-int bm_valu_probe(uint32_t mix, uint32_t iters, float *d_out, size_t n_out, void *stream,
-                  double *lane_ops_per_s);
 
 #ifdef __cplusplus
 }

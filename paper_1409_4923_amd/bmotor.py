@@ -43,12 +43,27 @@ class bm_run(ctypes.Structure):
                 ("dt", ctypes.c_double), ("n_steps", ctypes.c_uint64), ("window_start", ctypes.c_uint64),
                 ("n_paths", ctypes.c_uint64), ("seed", ctypes.c_uint64),
                 ("x0_lo", ctypes.c_double), ("x0_hi", ctypes.c_double),
-                ("v0_lo", ctypes.c_double), ("v0_hi", ctypes.c_double)]
+                ("v0_lo", ctypes.c_double), ("v0_hi", ctypes.c_double),
+                ("step_tol", ctypes.c_double), ("max_halvings", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
 
 
 class bm_stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("n_nonfinite", ctypes.c_uint64), ("mean", ctypes.c_double),
                 ("var", ctypes.c_double), ("se", ctypes.c_double), ("t_window", ctypes.c_double)]
+
+
+class bm_path(ctypes.Structure):
+    _fields_ = [("periods", ctypes.c_int64), ("x", ctypes.c_double), ("v", ctypes.c_double),
+                ("periods_window", ctypes.c_int64), ("x_window", ctypes.c_double),
+                ("kick_frac", ctypes.c_double), ("noise", ctypes.c_int64 * 5),
+                ("step_level", ctypes.c_int64), ("steps_taken", ctypes.c_int64)]
+
+
+# numpy view of an array of bm_path records
+PATH_RECORD_FIELDS = [("periods", "<i8"), ("x", "<f8"), ("v", "<f8"), ("periods_window", "<i8"),
+                      ("x_window", "<f8"), ("kick_frac", "<f8"), ("noise", "<i8", (5,)),
+                      ("step_level", "<i8"), ("steps_taken", "<i8")]
+PATH_BYTES = ctypes.sizeof(bm_path)
 
 
 class bm_tune(ctypes.Structure):
@@ -81,7 +96,8 @@ SIGNATURES = [
     ("bm_integrate", ctypes.c_int, [_vp, ctypes.c_uint64]),
     ("bm_ensemble_steps", ctypes.c_int, [_vp, _P(ctypes.c_uint64)]),
     ("bm_reduce", ctypes.c_int, [_vp, _vp]),
-    ("bm_read_paths", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_uint64, _vp, _vp, _vp, _vp]),
+    ("bm_read_paths", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp]),
+    ("bm_write_paths", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_uint64, _vp]),
     ("bm_density", ctypes.c_int, [_vp, ctypes.c_uint32, _vp]),
     ("bm_scan_workspace_size", ctypes.c_int, [_P(bm_model), _P(bm_run), _sz, _P(_sz)]),
     ("bm_scan_plan_create", ctypes.c_int, [_P(bm_model), _P(bm_run), _sz, _P(bm_tune), _vp, _sz, _vp, _vp,
@@ -93,18 +109,19 @@ SIGNATURES = [
                                         _P(bm_tune), _P(ctypes.c_float)]),
     ("bm_tune_set_default", ctypes.c_int, [ctypes.c_uint32] * 4 + [_P(bm_tune)]),
     ("bm_tune_get_default", ctypes.c_int, [ctypes.c_uint32] * 4 + [_P(bm_tune)]),
+    ("bm_tune_lookup", ctypes.c_int, [ctypes.c_uint32] * 4 + [_P(bm_tune)]),
+    ("bm_tune_save", ctypes.c_int, [ctypes.c_char_p]),
+    ("bm_tune_load", ctypes.c_int, [ctypes.c_char_p, _P(ctypes.c_uint32)]),
     ("bm_mlp_workspace_size", ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, _P(_sz)]),
     ("bm_mlp_init", ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint64, _vp, _vp]),
     ("bm_mlp_cast", ctypes.c_int, [ctypes.c_uint32, _vp, _vp, _vp]),
     ("bm_mlp_forward", ctypes.c_int, [ctypes.c_uint32, _vp, _vp, _vp, ctypes.c_uint64, _vp, _vp, _sz, _vp]),
     ("bm_mlp_backward", ctypes.c_int, [ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint64, _vp, _vp, _vp,
                                        _sz, _vp]),
-    ("bm_mlp_adam", ctypes.c_int, [ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint32, ctypes.c_float,
+    ("bm_mlp_adam_step", ctypes.c_int, [ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, ctypes.c_uint32, ctypes.c_float,
                                    ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp]),
     ("bm_surrogate_query", ctypes.c_int, [ctypes.c_uint32, _vp, _vp, _vp, ctypes.c_uint64, ctypes.c_float, _vp,
                                           _vp, _vp, _vp, _vp, _sz, _vp]),
-    ("bm_valu_probe", ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, _vp, _sz, _vp,
-                                     ctypes.POINTER(ctypes.c_double)]),
 ]
 
 BM_MLP_INPUTS, BM_MLP_HIDDEN, BM_MLP_PARAMS, BM_MLP_BF16, BM_MLP_MAX_MEMBERS = 5, 256, 133377, 132608, 16
@@ -217,8 +234,12 @@ def bm_density(h: int, n_bins: int, d_counts: int) -> None:
 
 
 def bm_read_paths(h: int, first: int, count: int, d_x: int | None, d_v: int | None,
-                  d_noise: int | None, d_vp: int | None) -> None:
-    check(lib().bm_read_paths(h, first, count, d_x, d_v, d_noise, d_vp))
+                  d_noise: int | None, d_vp: int | None, d_state: int | None = None) -> None:
+    check(lib().bm_read_paths(h, first, count, d_x, d_v, d_noise, d_vp, d_state))
+
+
+def bm_write_paths(h: int, first: int, count: int, d_state: int) -> None:
+    check(lib().bm_write_paths(h, first, count, d_state))
 
 
 # ---------------------------------------------------------------------------
@@ -257,6 +278,24 @@ class Ensemble:
                                         self.stream.cuda_stream)
         if tune is not None:
             bm_ensemble_set_tune(self.h, tune)
+
+    @classmethod
+    def resume(cls, model: bm_model, run: bm_run, steps_done: int, tune: bm_tune | None = None, device=None):
+        """An ensemble opened at `steps_done` on a fresh workspace whose paths hold no
+        state yet: every path is to be written with write_state before integrating."""
+        import torch
+        self = cls.__new__(cls)
+        self.torch = torch
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        self.model, self.run = model, run
+        self.ws_bytes = bm_ensemble_workspace_size(model, run)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.h = bm_ensemble_attach(model, run, self.ws.data_ptr(), self.ws_bytes, int(steps_done),
+                                    self.stream.cuda_stream)
+        if tune is not None:
+            bm_ensemble_set_tune(self.h, tune)
+        return self
 
     def checkpoint(self, device="cpu"):
         """(copy of the workspace, steps done): the whole state of the ensemble."""
@@ -302,6 +341,28 @@ class Ensemble:
         bm_density(self.h, counts.numel(), counts.data_ptr())
         return counts
 
+    def read_state(self, first: int = 0, count: int | None = None):
+        """bm_path records of paths [first, first + count) as a uint8 device tensor
+        (count x PATH_BYTES); `records()` turns it into a numpy structured array."""
+        torch = self.torch
+        count = self.run.n_paths - first if count is None else count
+        st = torch.empty(max(count, 1) * PATH_BYTES, dtype=torch.uint8, device=self.device)
+        bm_read_paths(self.h, first, count, None, None, None, None, st.data_ptr())
+        return st[: count * PATH_BYTES]
+
+    def write_state(self, state, first: int = 0):
+        """Write bm_path records (a uint8 device tensor from read_state, or a numpy
+        structured array of PATH_RECORD_FIELDS) into paths first, first + 1, ..."""
+        torch = self.torch
+        if not isinstance(state, torch.Tensor):
+            import numpy as np
+            state = torch.from_numpy(np.ascontiguousarray(state).view(np.uint8).reshape(-1))
+        state = state.to(self.device).contiguous()
+        if state.numel() % PATH_BYTES:
+            raise ValueError("state holds %d bytes, not a whole number of bm_path records" % state.numel())
+        bm_write_paths(self.h, first, state.numel() // PATH_BYTES, state.data_ptr())
+        self._keep = state          # the copy is enqueued on the stream: keep the source alive
+
     def read(self, first: int = 0, count: int | None = None) -> PathState:
         torch = self.torch
         count = self.run.n_paths - first if count is None else count
@@ -312,6 +373,13 @@ class Ensemble:
         bm_read_paths(self.h, first, count, x.data_ptr(), v.data_ptr(), nz.data_ptr(), vp.data_ptr())
         self.stream.synchronize()
         return PathState(x.cpu(), v.cpu(), nz.cpu(), vp.cpu())
+
+
+def records(state):
+    """numpy structured array (PATH_RECORD_FIELDS) of a read_state tensor."""
+    import numpy as np
+    raw = state.cpu().numpy() if hasattr(state, "cpu") else np.asarray(state, dtype=np.uint8)
+    return raw.view(np.dtype(PATH_RECORD_FIELDS))
 
 
 def stats_from_bytes(b: bytes) -> bm_stats:
@@ -377,6 +445,45 @@ def bm_tune_get_default(dyn: int, pot: int, noise: int, prec: int) -> bm_tune:
     t = bm_tune()
     check(lib().bm_tune_get_default(dyn, pot, noise, prec, ctypes.byref(t)))
     return t
+
+
+def bm_tune_lookup(dyn: int, pot: int, noise: int, prec: int):
+    """The launch shape set, tuned or loaded for this key, or None if only the
+    built-in default applies."""
+    t = bm_tune()
+    rc = lib().bm_tune_lookup(dyn, pot, noise, prec, ctypes.byref(t))
+    if rc == BM_ERR_STATE:
+        return None
+    check(rc)
+    return t
+
+
+def bm_tune_save(path: str) -> None:
+    check(lib().bm_tune_save(os.fsencode(path)))
+
+
+def bm_tune_load(path: str) -> int:
+    n = ctypes.c_uint32()
+    check(lib().bm_tune_load(os.fsencode(path), ctypes.byref(n)))
+    return int(n.value)
+
+
+def autotune_cached(models, runs, max_steps: int, d_ws: int, ws_bytes: int, d_results: int, stream: int,
+                    cache: str):
+    """Launch shape for the scan of (models, runs): taken from the JSON cache file
+    `cache` when it holds one for this model family and device (no timing), else
+    found by bm_scan_autotune and added to the file.  Returns (bm_tune, ms or None)."""
+    m0, r0 = models[0], runs[0]
+    if os.path.exists(cache):
+        bm_tune_load(cache)
+        t = bm_tune_lookup(m0.dyn, m0.pot, m0.noise, r0.prec)
+        if t is not None:
+            return t, None
+    t, ms = bm_scan_autotune(models, runs, max_steps, d_ws, ws_bytes, d_results, stream)
+    d = os.path.dirname(os.path.abspath(cache))
+    os.makedirs(d, exist_ok=True)
+    bm_tune_save(cache)
+    return t, ms
 
 
 def stats_array_from_bytes(b: bytes, n: int):
@@ -447,23 +554,15 @@ def bm_mlp_backward(n_members, d_params, d_wbf, d_x, d_t, d_idx, batch, d_grad, 
                                 ws_bytes, stream))
 
 
-def bm_mlp_adam(n_members, d_params, d_grad, d_m, d_v, d_wbf, step, lr, beta1=0.9, beta2=0.999, eps=1e-8,
+def bm_mlp_adam_step(n_members, d_params, d_grad, d_m, d_v, d_wbf, step, lr, beta1=0.9, beta2=0.999, eps=1e-8,
                 stream=None) -> None:
-    check(lib().bm_mlp_adam(n_members, d_params, d_grad, d_m, d_v, d_wbf, step, lr, beta1, beta2, eps, stream))
+    check(lib().bm_mlp_adam_step(n_members, d_params, d_grad, d_m, d_v, d_wbf, step, lr, beta1, beta2, eps, stream))
 
 
 def bm_surrogate_query(n_members, d_params, d_wbf, d_x, batch, threshold, d_mean, d_std, d_fidx, d_fcount, d_ws,
                        ws_bytes, stream) -> None:
     check(lib().bm_surrogate_query(n_members, d_params, d_wbf, d_x, batch, threshold, d_mean, d_std, d_fidx,
                                    d_fcount, d_ws, ws_bytes, stream))
-
-
-def bm_valu_probe(mix: int, iters: int, d_out: int, n_out: int, stream: int) -> float:
-    """Vector-ALU issue rate (lane-ops/s) of the device for mix 0 (FMA chains) or 1
-    (FMA + compare + select); d_out: n_out device floats (a multiple of 256)."""
-    r = ctypes.c_double(0.0)
-    check(lib().bm_valu_probe(mix, iters, d_out, n_out, stream, ctypes.byref(r)))
-    return r.value
 
 
 class Surrogate:
@@ -523,7 +622,7 @@ class Surrogate:
 
     def adam(self, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
         self.step += 1
-        bm_mlp_adam(self.n, self.params.data_ptr(), self.grad.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+        bm_mlp_adam_step(self.n, self.params.data_ptr(), self.grad.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
                     self.wbf.data_ptr(), self.step, lr, beta1, beta2, eps, self.stream.cuda_stream)
 
     def query(self, x, threshold: float):

@@ -37,8 +37,12 @@ SOURCES = [
     ("scan_f64_od.hip", []),
     ("scan_f64_in.hip", []),
     ("mlp.hip", []),
-    ("probe.hip", []),
 ]
+
+# The vector-ALU issue-rate probe (a measurement aid of the benchmark, not part of
+# the method) is a library of its own.
+PROBE_SRC = "probe.hip"
+PROBE_LIB = os.path.join(HERE, "libbmprobe.so")
 
 
 def sources() -> list[str]:
@@ -46,11 +50,12 @@ def sources() -> list[str]:
 
 
 def build_library(verbose: bool = False, jobs: int | None = None) -> str:
-    """Compile every translation unit (in parallel) and link libbmotor.so."""
+    """Compile every translation unit (in parallel), link libbmotor.so and the
+    benchmark's libbmprobe.so."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 1)
     objs, procs = [], []
-    pending = list(SOURCES)
+    pending = list(SOURCES) + [(PROBE_SRC, [])]
     while pending or procs:
         while pending and len(procs) < jobs:
             src, extra = pending.pop(0)
@@ -68,10 +73,12 @@ def build_library(verbose: bool = False, jobs: int | None = None) -> str:
             raise RuntimeError("hipcc failed on %s:\n%s" % (src, out.decode(errors="replace")))
         if verbose and out:
             print(out.decode(errors="replace"), flush=True)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    probe_obj = os.path.join(BUILD_DIR, PROBE_SRC.replace(".hip", ".o"))
+    for lib, parts in ((LIB, [o for o in objs if o != probe_obj]), (PROBE_LIB, [probe_obj])):
+        tmp = lib + ".tmp%d" % os.getpid()
+        cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + parts
+        subprocess.check_call(cmd)
+        os.replace(tmp, lib)
     return LIB
 
 

@@ -115,8 +115,21 @@ int validate(const bm_model *m, const bm_run *r)
     if (!(fin(r->v0_lo) && fin(r->v0_hi) && r->v0_lo <= r->v0_hi))
         return fail(BM_ERR_INVALID_ARG, "need finite v0_lo <= v0_hi");
     if (r->window_start > 0xFFFFFFFFull) return fail(BM_ERR_INVALID_ARG, "window_start >= 2^32");
+    if (!(fin(r->step_tol) && r->step_tol >= 0)) return fail(BM_ERR_INVALID_ARG, "step_tol must be finite and >= 0");
+    if (r->pad != 0) return fail(BM_ERR_INVALID_ARG, "bm_run.pad must be 0");
+    if (r->step_tol > 0) {
+        if (r->max_halvings < 1 || r->max_halvings > SC_MAX_HALVINGS)
+            return fail(BM_ERR_INVALID_ARG, "max_halvings must be in [1, %u] with step_tol > 0", SC_MAX_HALVINGS);
+        if (m->noise & (BM_NOISE_NORMAL | BM_NOISE_JUMP_GRID))
+            return fail(BM_ERR_UNSUPPORTED, "step control runs the three-point scheme with jumps on the dt grid");
+    } else if (r->max_halvings != 0) {
+        return fail(BM_ERR_INVALID_ARG, "max_halvings must be 0 without step control (step_tol = 0)");
+    }
     return BM_OK;
 }
+
+// Step-size control on chi is requested.
+static bool step_control(const bm_run *r) { return r->step_tol > 0; }
 
 double step_of(const bm_model *m, const bm_run *r)
 {
@@ -124,14 +137,20 @@ double step_of(const bm_model *m, const bm_run *r)
                                    : r->dt;
 }
 
-// Entries of the forcing table: one drive period plus one block of 16 steps.
-size_t table_entries(const bm_run *r) { return (r->steps_per_period ? r->steps_per_period : 1u) + 16; }
+// Entries of the forcing table: one drive period plus one block of 16 steps; under
+// step control one period on the grid of the smallest step (2^max_halvings entries
+// per step of dt) plus 16.
+size_t table_entries(const bm_run *r)
+{
+    const size_t per = r->steps_per_period ? r->steps_per_period : 1u;
+    return (step_control(r) ? per << r->max_halvings : per) + 16;
+}
 
 // ---------------------------------------------------------------------------
 // Workspace layout (structure of arrays, each 256-byte aligned)
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t x, w, v, xi, wi, sP, kP, thP, sD, mD, d, vp, part, tab, total;
+    size_t x, w, v, xi, wi, sP, kP, thP, sD, mD, d, lev, kA, vp, part, tab, total;
 };
 
 static size_t up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -154,6 +173,8 @@ static Layout layout(const bm_model *m, const bm_run *r)
     L.sD = take(N * 4);
     L.mD = take(N * 4);
     L.d = take(N * 4);
+    L.lev = step_control(r) ? take(N * 4) : 0;
+    L.kA = step_control(r) ? take(N * 4) : 0;
     L.vp = take(N * 8);
     L.part = take(((N + 63) / 64) * sizeof(Partial));
     L.tab = take(table_entries(r) * rs);
@@ -230,12 +251,15 @@ double forcing_constant(const bm_model *m)
 void forcing_table(const bm_model *m, const bm_run *r, std::vector<double> &tab)
 {
     const uint32_t spp = r->steps_per_period;
-    const uint32_t per = spp ? spp : 1u;
+    const size_t n = table_entries(r);
     const double c = forcing_constant(m);
-    tab.assign(per + 16, c);
-    for (uint32_t j = 0; j < per + 16 && spp; ++j) {
-        const uint32_t i = j % spp;
-        tab[j] = m->drive_amp * std::cos(2.0 * M_PI * (double)i / (double)spp) + c;
+    tab.assign(n, c);
+    if (!spp) return;
+    // the phase grid: spp entries per period, or spp 2^max_halvings under step control
+    const uint64_t period = step_control(r) ? (uint64_t)spp << r->max_halvings : spp;
+    for (size_t j = 0; j < n; ++j) {
+        const uint64_t i = j % period;
+        tab[j] = m->drive_amp * std::cos(2.0 * M_PI * (double)i / (double)period) + c;
     }
 }
 
@@ -317,6 +341,20 @@ static void fill_kargs(bm_ensemble *e)
     k.vp = (double *)(b + L.vp);
     k.part = (Partial *)(b + L.part);
     k.p = point_const(&e->model, &e->run, b + L.tab);
+    k.noise = e->model.noise;
+    if (step_control(&e->run)) {
+        k.lev = (int32_t *)(b + L.lev);
+        k.kA = (uint32_t *)(b + L.kA);
+        k.sc_J = e->run.max_halvings;
+        k.sc_tol = e->run.step_tol;
+        const bm_model *m = &e->model;
+        const double G = !(m->noise & BM_NOISE_GAUSS) ? 0.0
+                        : m->dyn == BM_INERTIAL ? std::sqrt(2.0 * m->gamma * m->D) : std::sqrt(2.0 * m->D);
+        for (uint32_t l = 0; l <= k.sc_J; ++l) {
+            k.sc_h[l] = std::ldexp(k.p.dt, -(int)l);
+            k.sc_g3[l] = G * std::sqrt(3.0 * k.sc_h[l]);
+        }
+    }
 }
 
 static void fill_table(bm_ensemble *e)
@@ -405,6 +443,8 @@ extern "C" int bm_ensemble_set_tune(bm_ensemble *e, const bm_tune *t)
     const bm_tune use = t ? *t : default_tune(e->model.dyn, e->model.pot, e->model.noise, e->run.prec);
     int rc = check_tune(&use, e->model.noise, e->run.prec);
     if (rc) return rc;
+    if (t && step_control(&e->run) && use.paths_per_lane != 1)
+        return fail(BM_ERR_UNSUPPORTED, "step control runs one path per lane");
     e->ppl = use.paths_per_lane;
     e->block = use.block;
     return ok();
@@ -421,6 +461,13 @@ static hipError_t launch_advance(const bm_ensemble *e, const KArgs &k)
 {
     const int pot = (int)e->model.pot, noise = (int)e->model.noise;
     const int ppl = (int)e->ppl, blk = (int)e->block;
+    if (step_control(&e->run)) {                   // one path per lane, a wave per control group
+        if (e->run.prec == BM_F32)
+            return e->model.dyn == BM_INERTIAL ? launch_advance_sc_f32_in(pot, blk, k, e->stream)
+                                               : launch_advance_sc_f32_od(pot, blk, k, e->stream);
+        return e->model.dyn == BM_INERTIAL ? launch_advance_sc_f64_in(pot, blk, k, e->stream)
+                                           : launch_advance_sc_f64_od(pot, blk, k, e->stream);
+    }
     if (e->run.prec == BM_F32)
         return e->model.dyn == BM_INERTIAL ? launch_advance_f32_in(pot, noise, ppl, blk, k, e->stream)
                                            : launch_advance_f32_od(pot, noise, ppl, blk, k, e->stream);
@@ -482,27 +529,56 @@ extern "C" int bm_reduce(bm_ensemble *e, bm_stats *d_out)
     return ok();
 }
 
-extern "C" int bm_read_paths(bm_ensemble *e, uint64_t first, uint64_t count, double *d_x, double *d_v,
-                             int64_t *d_noise, double *d_vp)
+// Range of paths [first, first + count) inside the ensemble and the kernel arguments
+// restricted to the arrays its model has.
+static int path_range(const bm_ensemble *e, uint64_t first, uint64_t count, KArgs &k)
 {
-    if (!e) return fail(BM_ERR_INVALID_ARG, "NULL handle");
     if (first > e->run.n_paths || count > e->run.n_paths - first)
         return fail(BM_ERR_INVALID_ARG, "path range [%llu, +%llu) outside the ensemble",
                     (unsigned long long)first, (unsigned long long)count);
-    if (count == 0) return ok();
-    KArgs k = e->k;
+    k = e->k;
     k.n0 = first;
     k.n1 = count;
-    const int with_vp = e->n_done > e->run.window_start ? 1 : 0;
-    if (with_vp) set_window(e, k);
     const uint32_t noise = e->model.noise;
     if (!(noise & BM_NOISE_POISSON)) { k.sP = nullptr; k.kP = nullptr; }
     if (!(noise & BM_NOISE_DICH)) { k.sD = nullptr; k.mD = nullptr; k.d = nullptr; }
+    return BM_OK;
+}
+
+extern "C" int bm_read_paths(bm_ensemble *e, uint64_t first, uint64_t count, double *d_x, double *d_v,
+                             int64_t *d_noise, double *d_vp, bm_path *d_state)
+{
+    if (!e) return fail(BM_ERR_INVALID_ARG, "NULL handle");
+    KArgs k;
+    int rc = path_range(e, first, count, k);
+    if (rc) return rc;
+    if ((uintptr_t)d_state & 7u) return fail(BM_ERR_INVALID_ARG, "d_state must be 8-byte aligned");
+    if (count == 0) return ok();
+    const int with_vp = e->n_done > e->run.window_start ? 1 : 0;
+    if (with_vp) set_window(e, k);
     const int pot = (int)e->model.pot;
     hipError_t he = e->run.prec == BM_F32
-                         ? launch_read_f32(pot, k, d_x, d_v, d_noise, d_vp, with_vp, e->stream)
-                         : launch_read_f64(pot, k, d_x, d_v, d_noise, d_vp, with_vp, e->stream);
+                         ? launch_read_f32(pot, k, d_x, d_v, d_noise, d_vp, with_vp, d_state, e->stream)
+                         : launch_read_f64(pot, k, d_x, d_v, d_noise, d_vp, with_vp, d_state, e->stream);
     if (he != hipSuccess) return hip_fail(he, "export kernel launch");
+    return ok();
+}
+
+extern "C" int bm_write_paths(bm_ensemble *e, uint64_t first, uint64_t count, const bm_path *d_state)
+{
+    if (!e) return fail(BM_ERR_INVALID_ARG, "NULL handle");
+    KArgs k;
+    int rc = path_range(e, first, count, k);
+    if (rc) return rc;
+    if (!d_state || ((uintptr_t)d_state & 7u))
+        return fail(BM_ERR_INVALID_ARG, "d_state must be a non-NULL, 8-byte aligned device pointer");
+    if (count == 0) return ok();
+    const uint64_t nw = e->run.window_start;
+    const uint32_t snap = e->n_done > nw ? 2u : (e->n_done == nw ? 1u : 0u);
+    const int pot = (int)e->model.pot;
+    hipError_t he = e->run.prec == BM_F32 ? launch_write_f32(pot, k, d_state, snap, e->stream)
+                                          : launch_write_f64(pot, k, d_state, snap, e->stream);
+    if (he != hipSuccess) return hip_fail(he, "import kernel launch");
     return ok();
 }
 

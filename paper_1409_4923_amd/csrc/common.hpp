@@ -147,6 +147,15 @@ struct KArgs {
     uint32_t snapshot;    // store the window snapshot at the end of the launch
     uint32_t pad;
     double t_window;      // (n - n_window) dt for the velocity kernel
+    // step-size control on chi (0 halvings: off)
+    int32_t *lev;         // per path: current step dt / 2^lev (the same in a group of 64)
+    uint32_t *kA;         // per path: steps taken (index of the next Algorithm 2 draw)
+    uint32_t sc_J;        // most halvings
+    uint32_t noise;       // noise mask of the model
+    double sc_tol;        // tolerance on max(|chi_x|, |chi_v|)
+    double sc_h[9];       // step of each level, dt / 2^l
+    double sc_g3[9];      // its three-point size G sqrt(3 dt / 2^l)
 };
+constexpr uint32_t SC_MAX_HALVINGS = 8;
 
 } // namespace bm

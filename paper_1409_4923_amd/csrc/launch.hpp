@@ -2,6 +2,7 @@
 // precision and dynamics, defined in paths_<prec>_<dyn>.hip).
 #pragma once
 
+#include "bmotor.h"
 #include "common.hpp"
 
 namespace bm {
@@ -13,7 +14,8 @@ struct ScanArgs;
     hipError_t launch_advance_##SUF(int pot, int noise, int ppl, int block, const KArgs &a,       \
                                     hipStream_t s);                                                \
     hipError_t launch_scan_##SUF(int pot, int noise, int ppl, int block, int groups_per_cu,       \
-                                 int n_cu, const ScanArgs &a, hipStream_t s);
+                                 int n_cu, const ScanArgs &a, hipStream_t s);                       \
+    hipError_t launch_advance_sc_##SUF(int pot, int block, const KArgs &a, hipStream_t s);
 
 BM_DECLARE_LAUNCHERS(f32_od)
 BM_DECLARE_LAUNCHERS(f32_in)
@@ -27,8 +29,10 @@ hipError_t launch_velocity_f64(int pot, const KArgs &a, hipStream_t s);
 hipError_t launch_density_f32(int pot, const KArgs &a, uint32_t n_bins, unsigned long long *hist, hipStream_t s);
 hipError_t launch_density_f64(int pot, const KArgs &a, uint32_t n_bins, unsigned long long *hist, hipStream_t s);
 hipError_t launch_read_f32(int pot, const KArgs &a, double *x, double *v, int64_t *nz, double *vp,
-                           int with_vp, hipStream_t s);
+                           int with_vp, bm_path *st, hipStream_t s);
 hipError_t launch_read_f64(int pot, const KArgs &a, double *x, double *v, int64_t *nz, double *vp,
-                           int with_vp, hipStream_t s);
+                           int with_vp, bm_path *st, hipStream_t s);
+hipError_t launch_write_f32(int pot, const KArgs &a, const bm_path *st, uint32_t snap, hipStream_t s);
+hipError_t launch_write_f64(int pot, const KArgs &a, const bm_path *st, uint32_t snap, hipStream_t s);
 
 } // namespace bm

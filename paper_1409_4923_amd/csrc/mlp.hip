@@ -692,7 +692,7 @@ extern "C" int bm_mlp_backward(uint32_t n_members, const float *d_params, const 
     return e == hipSuccess ? ok() : hip_fail(e, "bm_mlp_backward");
 }
 
-extern "C" int bm_mlp_adam(uint32_t n_members, float *d_params, const float *d_grad, float *d_m, float *d_v,
+extern "C" int bm_mlp_adam_step(uint32_t n_members, float *d_params, const float *d_grad, float *d_m, float *d_v,
                            uint16_t *d_wbf, uint32_t step, float lr, float beta1, float beta2, float eps,
                            void *stream)
 {
@@ -711,34 +711,22 @@ extern "C" int bm_mlp_adam(uint32_t n_members, float *d_params, const float *d_g
     hipLaunchKernelGGL(k_adam, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, (hipStream_t)stream, d_params,
                        d_grad, d_m, d_v, (bf16_t *)d_wbf, total, lr, beta1, beta2, eps, c1, c2);
     hipError_t e = hipGetLastError();
-    return e == hipSuccess ? ok() : hip_fail(e, "bm_mlp_adam");
+    return e == hipSuccess ? ok() : hip_fail(e, "bm_mlp_adam_step");
 }
 
-extern "C" int bm_surrogate_query(uint32_t n_members, const float *d_params, const uint16_t *d_wbf,
-                                  const float *d_x, uint64_t batch, float threshold, float *d_mean, float *d_std,
-                                  uint32_t *d_fallback_idx, uint32_t *d_fallback_count, void *d_ws,
-                                  size_t ws_bytes, void *stream)
+// The kernels of a query: fused inference of every member into y, then mean, std,
+// routing flags and per-256-row counts (blk), their exclusive scan and the ordered
+// compaction of the routed rows.  Every element of y and blk a call reads is first
+// written by that call, so neither buffer needs clearing.
+static hipError_t enqueue_query(uint32_t n_members, const float *d_params, const uint16_t *d_wbf, const float *d_x,
+                                uint64_t batch, float threshold, float *d_mean, float *d_std,
+                                uint32_t *d_fallback_idx, uint32_t *d_fallback_count, float *y, uint32_t *blk,
+                                hipStream_t s)
 {
-    int rc = check_members(n_members);
-    if (rc) return rc;
-    if (!d_params || !d_wbf || !d_x || !d_mean || !d_std || !d_fallback_idx || !d_fallback_count)
-        return fail(BM_ERR_INVALID_ARG, "NULL pointer");
-    if (batch < 1 || batch > 0xFFFFFFFFull) return fail(BM_ERR_INVALID_ARG, "batch must be in [1, 2^32 - 1]");
-    if (!(threshold >= 0)) return fail(BM_ERR_INVALID_ARG, "threshold must be >= 0");
-    const MlpLayout L = mlp_layout(n_members, batch, false);
-    rc = check_ws(L, d_ws, ws_bytes);
-    if (rc) return rc;
-    int dev;
-    rc = check_device(&dev);
-    if (rc) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    char *ws = (char *)d_ws;
-    float *y = (float *)(ws + L.y);
     hipLaunchKernelGGL(k_mlp_infer<INFER_RT>, dim3((uint32_t)((batch + FROWS - 1) / FROWS), n_members),
                        dim3(64 * 8 / INFER_RT), 0, s, d_x, batch, (const bf16_t *)d_wbf, d_params, y, batch);
     hipError_t e = hipGetLastError();
     const uint64_t nblk = (batch + 255) / 256;
-    uint32_t *blk = (uint32_t *)(ws + L.blk);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_stats, dim3((uint32_t)nblk), dim3(256), 0, s, y, (int)n_members, batch, threshold,
                            d_mean, d_std, blk);
@@ -747,5 +735,40 @@ extern "C" int bm_surrogate_query(uint32_t n_members, const float *d_params, con
                            d_fallback_idx);
         e = hipGetLastError();
     }
+    return e;
+}
+
+static int check_query(uint32_t n_members, const float *d_params, const uint16_t *d_wbf, const float *d_x,
+                       uint64_t batch, float threshold, float *d_mean, float *d_std, uint32_t *d_fallback_idx,
+                       uint32_t *d_fallback_count)
+{
+    int rc = check_members(n_members);
+    if (rc) return rc;
+    if (!d_params || !d_wbf || !d_x || !d_mean || !d_std || !d_fallback_idx || !d_fallback_count)
+        return fail(BM_ERR_INVALID_ARG, "NULL pointer");
+    if (batch < 1 || batch > 0xFFFFFFFFull) return fail(BM_ERR_INVALID_ARG, "batch must be in [1, 2^32 - 1]");
+    if (!(threshold >= 0)) return fail(BM_ERR_INVALID_ARG, "threshold must be >= 0");
+    return BM_OK;
+}
+
+extern "C" int bm_surrogate_query(uint32_t n_members, const float *d_params, const uint16_t *d_wbf,
+                                  const float *d_x, uint64_t batch, float threshold, float *d_mean, float *d_std,
+                                  uint32_t *d_fallback_idx, uint32_t *d_fallback_count, void *d_ws,
+                                  size_t ws_bytes, void *stream)
+{
+    int rc = check_query(n_members, d_params, d_wbf, d_x, batch, threshold, d_mean, d_std, d_fallback_idx,
+                         d_fallback_count);
+    if (rc) return rc;
+    const MlpLayout L = mlp_layout(n_members, batch, false);
+    rc = check_ws(L, d_ws, ws_bytes);
+    if (rc) return rc;
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    char *ws = (char *)d_ws;
+    const hipError_t e = enqueue_query(n_members, d_params, d_wbf, d_x, batch, threshold, d_mean, d_std,
+                                       d_fallback_idx, d_fallback_count, (float *)(ws + L.y),
+                                       (uint32_t *)(ws + L.blk), (hipStream_t)stream);
     return e == hipSuccess ? ok() : hip_fail(e, "bm_surrogate_query");
 }
+

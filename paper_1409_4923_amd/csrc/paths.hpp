@@ -1,7 +1,7 @@
 // paths.hpp -- the per-path Monte Carlo step (Algorithms 1-4) as device code.
 //
 // One lane owns PPL paths; the whole path state lives in registers between the
-// load at kernel entry and the store at exit (Sec. 4, Memory optimization).
+// load at kernel entry and the store at exit (Sec. 5, Memory optimization).
 // Instantiated per (precision, dynamics, potential, noise mask, paths per lane)
 // so that each kernel contains only the arithmetic of its model.
 #pragma once
@@ -80,13 +80,19 @@ template <int POT> __device__ __forceinline__ float force_plus(float x, float A,
 // split into three doubles (the first two of 33 significant bits, so k times each is
 // exact for |k| < 2^20), r in [-pi/4, pi/4]; then the Taylor series of sin r to r^17
 // and of cos r to r^16 (remainders below 1e-19 and 3e-18 on that interval), and k
-// mod 4 picks cos r, -sin r, -cos r or sin r.  Arguments with |y| >= 2^20 (or NaN) in
-// any lane of the wave send the whole wave to the library cos.
+// mod 4 picks cos r, -sin r, -cos r or sin r.  A lane whose argument has |y| >= 2^20
+// (or is NaN) takes the library cos instead; the other lanes keep the polynomial, so
+// a path's value never depends on the paths that share its wave.
 __device__ __noinline__ double cos_library(double y) { return cos(y); }
 
-__device__ __forceinline__ double cos_fp64(double y)
+__device__ __forceinline__ double cos_fp64(double y_in)
 {
-    if (__builtin_amdgcn_ballot_w64(!(fabs(y) < 0x1p20)) != 0) return cos_library(y);
+    const bool big = !(fabs(y_in) < 0x1p20);
+    double lib = 0.0;
+    if (__builtin_amdgcn_ballot_w64(big) != 0) {
+        if (big) lib = cos_library(y_in);
+    }
+    const double y = big ? 0.0 : y_in;                               // keeps the reduction exact
     const double k = rint(y * 0x1.45f306dc9c883p-1);                 // 2/pi
     double r = fma(-k, 0x1.921fb544p+0, y);                          // pi/2, first 33 bits
     r = fma(-k, 0x1.0b4611a6p-34, r);                                //       next 33 bits
@@ -113,7 +119,8 @@ __device__ __forceinline__ double cos_fp64(double y)
     const double cs = fma(r2, pc, 1.0);
     const int q = (int)k & 3;                                        // k mod 4 (two's complement)
     const double v = (q & 1) ? sn : cs;
-    return (q == 1 || q == 2) ? -v : v;
+    const double poly = (q == 1 || q == 2) ? -v : v;
+    return big ? lib : poly;
 }
 
 template <int POT> __device__ __forceinline__ double force_plus(double x, double A, double kp)
@@ -167,7 +174,7 @@ template <int POT> constexpr double pot_offset()
 template <int POT> constexpr double period() { return POT == POT_TENT ? 2.0 : 1.0; }
 
 // ---------------------------------------------------------------------------
-// Folding of x modulo L (Sec. 4, Instruction optimization).
+// Folding of x modulo L (Sec. 5, Instruction optimization).
 // ---------------------------------------------------------------------------
 template <int POT, typename R> __device__ __forceinline__ void fold(Path<R> &s)
 {
@@ -408,6 +415,41 @@ __device__ __forceinline__ void pc_step(Path<R> &s, R h, R hh, R ngam, R kp, R d
         R xn = fma(f3, hh, xc);                                // corrector
         if constexpr (KICK) xn = xn + z;
         s.x = xn;
+    }
+}
+
+// Algorithm 1 as pc_step (no kick), also returning the local error estimate of the
+// paragraph after the algorithm: chi = predictor - corrector, as max(|chi_x|, |chi_v|)
+// for the inertial state (x, v).
+template <int DYN, int POT, typename R>
+__device__ __forceinline__ R pc_step_chi(Path<R> &s, R h, R hh, R ngam, R kp, R dxi, R A0, R A1)
+{
+    if constexpr (DYN == DYN_INERTIAL) {
+        const R x = s.x, v = s.v, vd = v + dxi;
+        const R f1 = fma(ngam, v, force_plus<POT>(x, A0, kp));
+        const R xb = fma(v, h, x);                             // Euler
+        const R vb = fma(f1, h, vd);
+        const R f2 = fma(ngam, vb, force_plus<POT>(xb, A1, kp));
+        const R xc = fma(v, hh, x), vc = fma(f1, hh, vd);      // y_n + F1 dt/2
+        const R xp = fma(vb, hh, xc);                          // predictor
+        const R vpr = fma(f2, hh, vc);
+        const R f3 = fma(ngam, vpr, force_plus<POT>(xp, A1, kp));
+        const R xn = fma(vpr, hh, xc);                         // corrector
+        const R vn = fma(f3, hh, vc);
+        s.x = xn;
+        s.v = vn;
+        return fmax(fabs(xp - xn), fabs(vpr - vn));
+    } else {
+        const R x = s.x, xd = x + dxi;
+        const R f1 = force_plus<POT>(x, A0, kp);
+        const R xb = fma(f1, h, xd);                           // Euler
+        const R f2 = force_plus<POT>(xb, A1, kp);
+        const R xc = fma(f1, hh, xd);                          // y_n + F1 dt/2
+        const R xp = fma(f2, hh, xc);                          // predictor
+        const R f3 = force_plus<POT>(xp, A1, kp);
+        const R xn = fma(f3, hh, xc);                          // corrector
+        s.x = xn;
+        return fabs(xp - xn);
     }
 }
 

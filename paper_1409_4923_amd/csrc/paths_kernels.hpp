@@ -4,6 +4,7 @@
 // translation unit (paths_f32.hip, paths_f64.hip), which instantiate them.
 #pragma once
 
+#include "bmotor.h"
 #include "paths.hpp"
 #include "reduce.hpp"
 
@@ -554,6 +555,7 @@ __global__ void __launch_bounds__(256) k_init(const KArgs a)
     if constexpr ((NOISE & NZ_JGRID) != 0) a.thP[p] = s.thP;
     if constexpr ((NOISE & NZ_DICH) != 0) { a.d[p] = s.d; a.sD[p] = s.sD; a.mD[p] = s.mD; }
     if (a.snapshot) { arr<R>(a.xi)[p] = s.x; a.wi[p] = s.w; }
+    if (a.lev) { a.lev[p] = (int32_t)a.sc_J; a.kA[p] = 0u; }   // step control starts at the smallest step
 }
 
 // ---------------------------------------------------------------------------
@@ -581,11 +583,12 @@ __global__ void __launch_bounds__(256) k_velocity(const KArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Export of paths [n0, n0 + n1) (n0/n1 reused as first/count) to FP64 arrays.
+// Export of paths [n0, n0 + n1) (n0/n1 reused as first/count) to FP64 arrays and
+// to lossless per-path records (every field widened exactly).
 // ---------------------------------------------------------------------------
 template <typename R, int POT>
 __global__ void __launch_bounds__(256) k_read(const KArgs a, double *xo, double *vo, int64_t *no,
-                                              double *vpo, int with_vp)
+                                              double *vpo, int with_vp, bm_path *so)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n1) return;
@@ -593,17 +596,70 @@ __global__ void __launch_bounds__(256) k_read(const KArgs a, double *xo, double 
     const double L = period<POT>();
     if (xo) xo[i] = (double)a.w[p] * L + (double)arr<R>(a.x)[p];
     if (vo) vo[i] = (double)arr<R>(a.v)[p];
+    const int64_t nz[5] = {a.sP ? a.sP[p] : 0, a.kP ? (int64_t)a.kP[p] : 0, a.sD ? a.sD[p] : 0,
+                           a.mD ? (int64_t)a.mD[p] : 0, a.d ? a.d[p] : 0};
     if (no) {
-        no[5 * i + 0] = a.sP ? a.sP[p] : 0;
-        no[5 * i + 1] = a.kP ? (int64_t)a.kP[p] : 0;
-        no[5 * i + 2] = a.sD ? a.sD[p] : 0;
-        no[5 * i + 3] = a.mD ? (int64_t)a.mD[p] : 0;
-        no[5 * i + 4] = a.d ? a.d[p] : 0;
+        for (int j = 0; j < 5; ++j) no[5 * i + j] = nz[j];
     }
     if (vpo && with_vp) {
         const double dx = (double)(a.w[p] - a.wi[p]) * L +
                           ((double)arr<R>(a.x)[p] - (double)arr<R>(a.xi)[p]);
         vpo[i] = dx / a.t_window;
+    }
+    if (so) {
+        bm_path r;
+        r.periods = a.w[p];
+        r.x = (double)arr<R>(a.x)[p];
+        r.v = (double)arr<R>(a.v)[p];
+        r.periods_window = a.wi[p];
+        r.x_window = (double)arr<R>(a.xi)[p];
+        r.kick_frac = a.thP ? a.thP[p] : 0.0;
+        for (int j = 0; j < 5; ++j) r.noise[j] = nz[j];
+        r.step_level = a.lev ? a.lev[p] : 0;
+        r.steps_taken = a.kA ? (int64_t)a.kA[p] : 0;
+        so[i] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Import of records into paths [n0, n0 + n1): the inverse of k_read's records.
+// Out-of-range values are clamped so that the path kernels' assumptions (countdowns
+// and counts in range, state 0/1, a kick fraction in [0, 1)) hold whatever the input.
+// snap: 0 leave the window snapshot, 1 set it to the written position, 2 take it
+// from the record.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t clamp_i32(int64_t v, int64_t lo, int64_t hi)
+{
+    return (int32_t)(v < lo ? lo : (v > hi ? hi : v));
+}
+
+template <typename R, int POT>
+__global__ void __launch_bounds__(256) k_write(const KArgs a, const bm_path *si, uint32_t snap)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n1) return;
+    const uint64_t p = a.n0 + i;
+    const bm_path r = si[i];
+    const int32_t w = clamp_i32(r.periods, INT32_MIN, INT32_MAX);
+    arr<R>(a.x)[p] = (R)r.x;
+    a.w[p] = w;
+    arr<R>(a.v)[p] = (R)r.v;
+    if (snap == 1u) {
+        arr<R>(a.xi)[p] = (R)r.x;
+        a.wi[p] = w;
+    } else if (snap == 2u) {
+        arr<R>(a.xi)[p] = (R)r.x_window;
+        a.wi[p] = clamp_i32(r.periods_window, INT32_MIN, INT32_MAX);
+    }
+    if (a.sP) a.sP[p] = clamp_i32(r.noise[0], 0, INT32_MAX);
+    if (a.kP) a.kP[p] = (uint32_t)(r.noise[1] < 0 ? 0 : (r.noise[1] > (int64_t)UINT32_MAX ? UINT32_MAX : r.noise[1]));
+    if (a.thP) a.thP[p] = (r.kick_frac >= 0.0 && r.kick_frac < 1.0) ? r.kick_frac : 0.0;
+    if (a.sD) a.sD[p] = clamp_i32(r.noise[2], 0, INT32_MAX);
+    if (a.mD) a.mD[p] = (uint32_t)(r.noise[3] < 0 ? 0 : (r.noise[3] > (int64_t)UINT32_MAX ? UINT32_MAX : r.noise[3]));
+    if (a.d) a.d[p] = r.noise[4] != 0 ? 1 : 0;
+    if (a.lev) {
+        a.lev[p] = clamp_i32(r.step_level, 0, (int64_t)a.sc_J);
+        a.kA[p] = (uint32_t)(r.steps_taken < 0 ? 0 : (r.steps_taken > (int64_t)UINT32_MAX ? UINT32_MAX : r.steps_taken));
     }
 }
 

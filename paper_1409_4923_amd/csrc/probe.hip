@@ -6,15 +6,37 @@
 // device issues for two instruction mixes: eight independent non-packed FP32 FMA
 // chains per lane, and the same with a compare and a select after every FMA (the
 // instruction classes of Algorithm 2's three-point increment).  It is not part of
-// the method.
+// the method: it is built into its own library, libbmprobe.so, which only the
+// benchmark's calibration loads.
+//
+//   int bmp_valu_probe(uint32_t mix, uint32_t iters, float *d_out, size_t n_out,
+//                      void *stream, double *lane_ops_per_s);
+//   const char *bmp_last_error(void);
+//
+// Runs n_out / 256 work-groups of 256 lanes, each lane carrying eight independent
+// non-packed FP32 FMA chains for `iters` iterations (mix 0), or each FMA followed
+// by a compare and a select (mix 1); d_out [n_out] (device, caller-owned) receives
+// one float per lane.  One warm-up launch, then the best of three timed launches
+// on `stream`; *lane_ops_per_s = lanes x iters x 8 x (1 or 3) / time.
+// Synchronises `stream`.  Returns 0, -1 for bad arguments (n_out a multiple of 256
+// in [256, 2^28], iters in [1, 2^24], mix 0 or 1, non-NULL pointers) or -4 when a
+// HIP call fails; bmp_last_error() gives the calling thread's message.
 #include <hip/hip_runtime.h>
 
-#include "bmotor.h"
-#include "host.hpp"
-
-using namespace bm::host;
+#include <cstdint>
+#include <cstdio>
+#include <string>
 
 namespace {
+
+thread_local std::string g_msg;
+
+int probe_fail(int code, const char *msg, hipError_t e = hipSuccess)
+{
+    g_msg = msg;
+    if (e != hipSuccess) { g_msg += ": "; g_msg += hipGetErrorString(e); }
+    return code;
+}
 
 constexpr int PROBE_CHAINS = 8;
 
@@ -40,19 +62,21 @@ __global__ void __launch_bounds__(256) k_valu_probe(float *out, float a, float b
 
 } // namespace
 
-extern "C" int bm_valu_probe(uint32_t mix, uint32_t iters, float *d_out, size_t n_out, void *stream,
-                             double *lane_ops_per_s)
+extern "C" const char *bmp_last_error(void) { return g_msg.c_str(); }
+
+extern "C" int bmp_valu_probe(uint32_t mix, uint32_t iters, float *d_out, size_t n_out, void *stream,
+                              double *lane_ops_per_s)
 {
-    if (mix > 1) return fail(BM_ERR_INVALID_ARG, "mix must be 0 (FMA) or 1 (FMA + compare + select)");
-    if (iters == 0 || iters > (1u << 24)) return fail(BM_ERR_INVALID_ARG, "iters must be in [1, 2^24]");
-    if (!d_out || !lane_ops_per_s) return fail(BM_ERR_INVALID_ARG, "d_out and lane_ops_per_s must not be NULL");
+    if (mix > 1) return probe_fail(-1, "mix must be 0 (FMA) or 1 (FMA + compare + select)");
+    if (iters == 0 || iters > (1u << 24)) return probe_fail(-1, "iters must be in [1, 2^24]");
+    if (!d_out || !lane_ops_per_s) return probe_fail(-1, "d_out and lane_ops_per_s must not be NULL");
     if (n_out < 256 || n_out % 256 != 0 || n_out / 256 > (1u << 20))
-        return fail(BM_ERR_INVALID_ARG, "n_out must be a multiple of 256 in [256, 2^28]");
+        return probe_fail(-1, "n_out must be a multiple of 256 in [256, 2^28]");
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         if (e0) (void)hipEventDestroy(e0);
-        return fail(BM_ERR_DEVICE, "hipEventCreate failed");
+        return probe_fail(-4, "hipEventCreate failed");
     }
     const unsigned blocks = (unsigned)(n_out / 256);
     float best = 0.0f;
@@ -72,8 +96,9 @@ extern "C" int bm_valu_probe(uint32_t mix, uint32_t iters, float *d_out, size_t 
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (he != hipSuccess) return hip_fail(he, "VALU probe");
+    if (he != hipSuccess) return probe_fail(-4, "VALU probe", he);
     const double ops_per_iter = PROBE_CHAINS * (mix ? 3.0 : 1.0);
     *lane_ops_per_s = (double)n_out * iters * ops_per_iter / (best * 1e-3);
-    return ok();
+    g_msg.clear();
+    return 0;
 }

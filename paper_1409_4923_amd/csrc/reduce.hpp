@@ -1,4 +1,4 @@
-// reduce.hpp -- FP64 ensemble statistics (eq. 31 over the paths; Sec. 3 1/sqrt(N)
+// reduce.hpp -- FP64 ensemble statistics (eq. 31 over the paths; Sec. 4 1/sqrt(N)
 // error): double-double sums of v_p and v_p^2 per 64-path chunk, combined in an
 // order that depends only on the number of chunks.  Compile with
 // -ffp-contract=off (error-free transformations).

@@ -4,11 +4,14 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <tuple>
+#include <unistd.h>
 #include <vector>
 
 #include "bmotor.h"
@@ -25,8 +28,36 @@ using namespace bm::host;
 // Launch shapes
 // ---------------------------------------------------------------------------
 namespace {
+// An installed launch shape and the device it was installed on.
+struct TuneEntry {
+    bm_tune t;
+    std::string arch;   // architecture name without feature suffixes ("" if unknown)
+    int cus;            // compute units
+};
+using TuneKey = std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>;
 std::mutex g_tune_mu;
-std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint32_t>, bm_tune> g_tune;
+std::map<TuneKey, TuneEntry> g_tune;
+
+// Architecture name (up to the first ':') and CU count of the current device.
+bool current_device(std::string &arch, int &cus)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+    arch.assign(prop.gcnArchName);
+    const size_t c = arch.find(':');
+    if (c != std::string::npos) arch.resize(c);
+    cus = prop.multiProcessorCount;
+    return true;
+}
+
+void install(const TuneKey &key, const bm_tune &t)
+{
+    TuneEntry e{t, std::string(), 0};
+    if (!current_device(e.arch, e.cus)) { e.arch.clear(); e.cus = 0; }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = e;
+}
 
 bm_tune builtin_tune()
 {
@@ -44,9 +75,11 @@ namespace host {
 
 bm_tune default_tune(uint32_t dyn, uint32_t pot, uint32_t noise, uint32_t prec)
 {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(std::make_tuple(dyn, pot, noise, prec));
-    if (it != g_tune.end()) return it->second;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(std::make_tuple(dyn, pot, noise, prec));
+        if (it != g_tune.end()) return it->second.t;
+    }
     bm_tune t = builtin_tune();
     // FP32 inertial paths without jump processes: two paths per lane give the step
     // loop independent work to interleave (measured 1.47 against 1.41e12 path-steps/s
@@ -96,8 +129,230 @@ extern "C" int bm_tune_set_default(uint32_t dyn, uint32_t pot, uint32_t noise, u
         return fail(BM_ERR_INVALID_ARG, "unknown model key");
     int rc = check_tune(t, noise, prec);
     if (rc) return rc;
+    install(std::make_tuple(dyn, pot, noise, prec), *t);
+    return ok();
+}
+
+extern "C" int bm_tune_lookup(uint32_t dyn, uint32_t pot, uint32_t noise, uint32_t prec, bm_tune *out)
+{
+    if (!out) return fail(BM_ERR_INVALID_ARG, "out must not be NULL");
+    if (dyn > BM_INERTIAL || pot > BM_POT_FREE || (noise & ~31u) || prec > BM_F32)
+        return fail(BM_ERR_INVALID_ARG, "unknown model key");
+    *out = default_tune(dyn, pot, noise, prec);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[std::make_tuple(dyn, pot, noise, prec)] = *t;
+    if (g_tune.find(std::make_tuple(dyn, pot, noise, prec)) == g_tune.end())
+        return fail(BM_ERR_STATE, "no shape installed for this model; the built-in default applies");
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Tuning cache file: a flat JSON document written by bm_tune_save.  The reader
+// accepts any JSON text whose "entries" member is an array of objects with
+// string / integer members, and ignores members it does not know.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Json {
+    const char *p, *end;
+    void ws() { while (p < end && (*p == ' ' || *p == '\n' || *p == '\t' || *p == '\r')) ++p; }
+    bool lit(char c) { ws(); if (p < end && *p == c) { ++p; return true; } return false; }
+    bool str(std::string &out)
+    {
+        ws();
+        if (p >= end || *p != '"') return false;
+        ++p;
+        out.clear();
+        while (p < end && *p != '"') {
+            if (*p == '\\') return false;           // the cache never holds escapes
+            out.push_back(*p++);
+        }
+        if (p >= end) return false;
+        ++p;
+        return true;
+    }
+    bool num(long long &v)
+    {
+        ws();
+        const char *q = p;
+        bool neg = false;
+        if (q < end && *q == '-') { neg = true; ++q; }
+        if (q >= end || *q < '0' || *q > '9') return false;
+        long long r = 0;
+        while (q < end && *q >= '0' && *q <= '9') {
+            if (r > 100000000000000LL) return false;
+            r = r * 10 + (*q++ - '0');
+        }
+        if (q < end && (*q == '.' || *q == 'e' || *q == 'E')) return false;   // integers only
+        p = q;
+        v = neg ? -r : r;
+        return true;
+    }
+    // Skips one value of any kind (nested objects / arrays, strings, numbers, literals).
+    bool skip(int depth = 0)
+    {
+        if (depth > 32) return false;
+        ws();
+        if (p >= end) return false;
+        std::string s;
+        long long n;
+        if (*p == '"') return str(s);
+        if (*p == '{' || *p == '[') {
+            const char close = *p == '{' ? '}' : ']';
+            const bool obj = *p == '{';
+            ++p;
+            if (lit(close)) return true;
+            do {
+                if (obj && !(str(s) && lit(':'))) return false;
+                if (!skip(depth + 1)) return false;
+            } while (lit(','));
+            return lit(close);
+        }
+        if (num(n)) return true;
+        for (const char *w : {"true", "false", "null"}) {
+            const size_t l = std::strlen(w);
+            if ((size_t)(end - p) >= l && std::strncmp(p, w, l) == 0) { p += l; return true; }
+        }
+        // a non-integer number
+        const char *q = p;
+        while (q < end && (std::strchr("+-.eE", *q) || (*q >= '0' && *q <= '9'))) ++q;
+        if (q == p) return false;
+        p = q;
+        return true;
+    }
+};
+
+struct FileEntry {
+    std::string arch;
+    long long cus = -1, dyn = -1, pot = -1, noise = -1, prec = -1, ppl = -1, block = -1, gpc = -1;
+};
+
+bool parse_entry(Json &j, FileEntry &e)
+{
+    if (!j.lit('{')) return false;
+    if (j.lit('}')) return true;
+    do {
+        std::string k;
+        if (!(j.str(k) && j.lit(':'))) return false;
+        long long *slot = k == "cus" ? &e.cus : k == "dyn" ? &e.dyn : k == "pot" ? &e.pot
+                        : k == "noise" ? &e.noise : k == "prec" ? &e.prec : k == "paths_per_lane" ? &e.ppl
+                        : k == "block" ? &e.block : k == "groups_per_cu" ? &e.gpc : nullptr;
+        if (k == "arch") {
+            if (!j.str(e.arch)) return false;
+        } else if (slot) {
+            if (!j.num(*slot)) return false;
+        } else if (!j.skip()) {
+            return false;
+        }
+    } while (j.lit(','));
+    return j.lit('}');
+}
+
+bool parse_file(const std::string &text, std::vector<FileEntry> &out)
+{
+    Json j{text.data(), text.data() + text.size()};
+    if (!j.lit('{')) return false;
+    bool seen = false;
+    if (!j.lit('}')) {
+        do {
+            std::string k;
+            if (!(j.str(k) && j.lit(':'))) return false;
+            if (k == "entries") {
+                seen = true;
+                if (!j.lit('[')) return false;
+                if (!j.lit(']')) {
+                    do {
+                        FileEntry e;
+                        if (!parse_entry(j, e)) return false;
+                        out.push_back(e);
+                    } while (j.lit(','));
+                    if (!j.lit(']')) return false;
+                }
+            } else if (!j.skip()) {
+                return false;
+            }
+        } while (j.lit(','));
+        if (!j.lit('}')) return false;
+    }
+    j.ws();
+    return seen && j.p == j.end;
+}
+
+} // namespace
+
+extern "C" int bm_tune_save(const char *path)
+{
+    if (!path || !*path) return fail(BM_ERR_INVALID_ARG, "path must not be empty");
+    std::string text = "{\"format\": \"libbmotor-tune\", \"version\": 1, \"entries\": [";
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        bool first = true;
+        for (const auto &kv : g_tune) {
+            const TuneEntry &e = kv.second;
+            if (e.arch.empty()) continue;                     // installed without a device
+            char buf[320];
+            std::snprintf(buf, sizeof buf,
+                          "%s\n  {\"arch\": \"%s\", \"cus\": %d, \"dyn\": %u, \"pot\": %u, \"noise\": %u, "
+                          "\"prec\": %u, \"paths_per_lane\": %u, \"block\": %u, \"groups_per_cu\": %u}",
+                          first ? "" : ",", e.arch.c_str(), e.cus, std::get<0>(kv.first), std::get<1>(kv.first),
+                          std::get<2>(kv.first), std::get<3>(kv.first), e.t.paths_per_lane, e.t.block,
+                          e.t.groups_per_cu);
+            text += buf;
+            first = false;
+        }
+    }
+    text += "\n]}\n";
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long long)getpid());
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return fail(BM_ERR_INVALID_ARG, "cannot write %s", tmp.c_str());
+    const bool wrote = std::fwrite(text.data(), 1, text.size(), f) == text.size();
+    const bool closed = std::fclose(f) == 0;
+    if (!wrote || !closed || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return fail(BM_ERR_INVALID_ARG, "cannot write %s", path);
+    }
+    return ok();
+}
+
+extern "C" int bm_tune_load(const char *path, uint32_t *n_loaded)
+{
+    if (!path || !*path) return fail(BM_ERR_INVALID_ARG, "path must not be empty");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(BM_ERR_INVALID_ARG, "cannot open %s", path);
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0 && text.size() < (1u << 24)) text.append(buf, n);
+    std::fclose(f);
+    std::vector<FileEntry> es;
+    if (!parse_file(text, es)) return fail(BM_ERR_INVALID_ARG, "%s is not a libbmotor tuning cache", path);
+    int dev;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    std::string arch;
+    int cus = 0;
+    if (!current_device(arch, cus)) return fail(BM_ERR_DEVICE, "cannot query the current device");
+    std::vector<std::pair<TuneKey, bm_tune>> use;
+    for (const FileEntry &e : es) {
+        if (e.arch != arch || e.cus != cus) continue;
+        const long long v[8] = {e.dyn, e.pot, e.noise, e.prec, e.ppl, e.block, e.gpc, e.cus};
+        for (long long x : v)
+            if (x < 0 || x > 0xFFFFFFFFLL) return fail(BM_ERR_INVALID_ARG, "%s: entry with a missing or bad field", path);
+        if (e.dyn > BM_INERTIAL || e.pot > BM_POT_FREE || (e.noise & ~31LL) || e.prec > BM_F32)
+            return fail(BM_ERR_INVALID_ARG, "%s: unknown model key", path);
+        bm_tune t;
+        t.size = sizeof(bm_tune);
+        t.paths_per_lane = (uint32_t)e.ppl;
+        t.block = (uint32_t)e.block;
+        t.groups_per_cu = (uint32_t)e.gpc;
+        rc = check_tune(&t, (uint32_t)e.noise, (uint32_t)e.prec);
+        if (rc) return fail(rc, "%s: %s", path, last_error_text());
+        use.emplace_back(std::make_tuple((uint32_t)e.dyn, (uint32_t)e.pot, (uint32_t)e.noise, (uint32_t)e.prec), t);
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const auto &u : use) g_tune[u.first] = TuneEntry{u.second, arch, cus};
+    }
+    if (n_loaded) *n_loaded = (uint32_t)use.size();
     return ok();
 }
 
@@ -144,6 +399,8 @@ int validate_scan(const bm_model *models, const bm_run *runs, size_t n)
         if (models[i].noise & (BM_NOISE_NORMAL | BM_NOISE_JUMP_GRID))
             return fail(BM_ERR_UNSUPPORTED,
                         "point %zu: the scan runs the three-point scheme on the fixed grid only", i);
+        if (runs[i].step_tol > 0)
+            return fail(BM_ERR_UNSUPPORTED, "point %zu: the scan runs fixed steps (step_tol must be 0)", i);
         if (runs[i].n_steps <= runs[i].window_start)
             return fail(BM_ERR_INVALID_ARG, "point %zu: n_steps must exceed window_start", i);
         if (runs[i].n_steps > 0xFFFFFFFFull) return fail(BM_ERR_UNSUPPORTED, "point %zu: n_steps >= 2^32", i);
@@ -412,9 +669,6 @@ extern "C" int bm_scan_autotune(const bm_model *models, const bm_run *runs, size
     if (result) return result;
     *best = bt;
     if (best_ms) *best_ms = best_t;
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[std::make_tuple(models[0].dyn, models[0].pot, noise, prec)] = bt;
-    }
+    install(std::make_tuple(models[0].dyn, models[0].pot, noise, prec), bt);
     return ok();
 }

@@ -1,6 +1,6 @@
 // scan_kernels.hpp -- persistent, work-stealing parameter scan (the paper's
 // "solve for multiple values of the system parameters in a single kernel call",
-// Sec. 4, Execution configuration optimizations).
+// Sec. 5, Execution configuration optimizations).
 //
 // Work items are (point, chunk of 64 * PPL paths), ordered longest-first on the
 // host.  Every wave of a persistent grid repeatedly claims the next item with one

@@ -1,7 +1,7 @@
 """Surrogate pipeline: labels from batched Monte Carlo scans, ensemble training,
 and queries answered by the surrogate or, where the members disagree, by Monte
 Carlo.  Orchestration only: every computation runs in libbmotor (bm_scan,
-bm_mlp_backward, bm_mlp_adam, bm_surrogate_query).
+bm_mlp_backward, bm_mlp_adam_step, bm_surrogate_query).
 """
 from __future__ import annotations
 

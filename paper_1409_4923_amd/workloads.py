@@ -47,6 +47,8 @@ class Workload:
     x0_hi: float = 1.0
     v0_lo: float = 0.0
     v0_hi: float = 0.0
+    step_tol: float = 0.0        # step-size control on chi (0: fixed step)
+    max_halvings: int = 0
 
     def step(self) -> float:
         return (2.0 * math.pi / self.omega) / self.spp if self.spp > 0 else self.dt
@@ -119,7 +121,7 @@ def to_c(w: Workload):
     r = B.make_run(prec=w.prec, steps_per_period=w.spp, point_id=w.point,
                    dt=(0.0 if w.spp > 0 else w.dt), n_steps=w.n_steps, window_start=w.n_window,
                    n_paths=w.n_paths, seed=w.seed, x0_lo=w.x0_lo, x0_hi=w.x0_hi,
-                   v0_lo=w.v0_lo, v0_hi=w.v0_hi)
+                   v0_lo=w.v0_lo, v0_hi=w.v0_hi, step_tol=w.step_tol, max_halvings=w.max_halvings)
     return m, r
 
 

@@ -49,7 +49,7 @@ def test_binding_covers_every_declared_symbol():
 
 
 def test_abi_version():
-    assert B.bm_abi_version() == 1
+    assert B.bm_abi_version() == 2
 
 
 _LAYOUT_C = r"""
@@ -62,6 +62,9 @@ int main(void) {
   printf("bm_run size %zu\n", sizeof(bm_run));
   printf("bm_stats size %zu\n", sizeof(bm_stats));
   printf("bm_tune size %zu\n", sizeof(bm_tune));
+  printf("bm_path size %zu\n", sizeof(bm_path));
+  F(bm_path, x) F(bm_path, periods_window) F(bm_path, kick_frac) F(bm_path, noise) F(bm_path, steps_taken)
+  F(bm_run, step_tol) F(bm_run, max_halvings)
   F(bm_model, gamma) F(bm_model, D) F(bm_model, dich_mub)
   F(bm_run, dt) F(bm_run, n_steps) F(bm_run, seed) F(bm_run, v0_hi)
   F(bm_stats, mean) F(bm_stats, t_window)
@@ -185,7 +188,8 @@ def test_null_arguments():
     assert L.bm_integrate(None, 10) == B.BM_ERR_INVALID_ARG
     assert L.bm_reduce(None, None) == B.BM_ERR_INVALID_ARG
     assert L.bm_ensemble_destroy(None) == B.BM_ERR_INVALID_ARG
-    assert L.bm_read_paths(None, 0, 1, None, None, None, None) == B.BM_ERR_INVALID_ARG
+    assert L.bm_read_paths(None, 0, 1, None, None, None, None, None) == B.BM_ERR_INVALID_ARG
+    assert L.bm_write_paths(None, 0, 1, None) == B.BM_ERR_INVALID_ARG
     assert L.bm_ensemble_set_tune(None, None) == B.BM_ERR_INVALID_ARG
 
 
@@ -293,3 +297,56 @@ def test_scan_plan_needs_device_and_workspace():
     if not has_gpu:
         assert L.bm_scan_plan_create(M, R, 4, None, 0x10000, need.value, 0x20000, None,
                                      ctypes.byref(h)) == B.BM_ERR_DEVICE
+
+
+def test_tune_lookup_reports_installed_shapes():
+    key = (B.BM_INERTIAL, B.BM_POT_TENT, B.BM_NOISE_DICH, B.BM_F64)
+    assert B.bm_tune_lookup(*key) is None                      # only the built-in default
+    B.bm_tune_set_default(*key, B.make_tune(1, 128, 3))
+    t = B.bm_tune_lookup(*key)
+    assert (t.paths_per_lane, t.block, t.groups_per_cu) == (1, 128, 3)
+
+
+def test_tune_cache_file_checks(tmp_path):
+    L = B.lib()
+    assert L.bm_tune_save(b"") == B.BM_ERR_INVALID_ARG
+    assert L.bm_tune_load(b"", None) == B.BM_ERR_INVALID_ARG
+    assert L.bm_tune_load(os.fsencode(str(tmp_path / "missing.json")), None) == B.BM_ERR_INVALID_ARG
+    # shapes installed without a device carry no architecture: the file holds none of them
+    B.bm_tune_set_default(B.BM_OVERDAMPED, B.BM_POT_SIN, B.BM_NOISE_GAUSS, B.BM_F32, B.make_tune(1, 64, 0))
+    out = tmp_path / "tune.json"
+    B.bm_tune_save(str(out))
+    import json
+    doc = json.loads(out.read_text())
+    assert doc["format"] == "libbmotor-tune" and doc["version"] == 1 and doc["entries"] == []
+    bad = ['', '{', '[]', '{"entries": {}}', '{"entries": [{"dyn": 1.5}]}', '{"entries": [}',
+           '{"format": "x"}', '{"entries": []} trailing', '{"entries": [{"arch": "a\\"b"}]}']
+    for i, text in enumerate(bad):
+        f = tmp_path / ("bad%d.json" % i)
+        f.write_text(text)
+        assert L.bm_tune_load(os.fsencode(str(f)), None) == B.BM_ERR_INVALID_ARG, text
+    good = tmp_path / "good.json"
+    good.write_text('{"version": 1, "note": [1, {"a": null}, -2.5e3], "entries": '
+                    '[{"arch": "gfx950", "cus": 256, "dyn": 1, "pot": 0, "noise": 1, "prec": 1, '
+                    '"paths_per_lane": 2, "block": 128, "groups_per_cu": 0, "extra": true}]}')
+    # a well-formed file gets as far as the device check
+    assert L.bm_tune_load(os.fsencode(str(good)), None) == B.BM_ERR_DEVICE
+
+
+def test_step_control_validation():
+    ok_m, ok_r = _ok_model_run(step_tol=1e-6, max_halvings=4)
+    assert _ws_rc(ok_m, ok_r)[0] == B.BM_OK
+    n_plain = _ws_rc(*_ok_model_run())[1]
+    assert _ws_rc(ok_m, ok_r)[1] > n_plain                   # control state and the finer table
+    for kw in (dict(step_tol=-1.0), dict(step_tol=float("nan")), dict(step_tol=1e-6, max_halvings=0),
+               dict(step_tol=1e-6, max_halvings=9), dict(max_halvings=2), dict(pad=1)):
+        m, r = _ok_model_run(**kw)
+        assert _ws_rc(m, r)[0] == B.BM_ERR_INVALID_ARG, kw
+    m, r = _ok_model_run(step_tol=1e-6, max_halvings=2, noise=B.BM_NOISE_NORMAL)
+    assert _ws_rc(m, r)[0] == B.BM_ERR_UNSUPPORTED
+    m, r = W.to_c(W.C2.with_(noise=W.GAUSS | W.POISSON | W.JUMP_GRID, step_tol=1e-6, max_halvings=2))
+    assert _ws_rc(m, r)[0] == B.BM_ERR_UNSUPPORTED
+    m, r = _ok_model_run(step_tol=1e-6, max_halvings=2)
+    n = ctypes.c_size_t()
+    assert B.lib().bm_scan_workspace_size(ctypes.byref(m), ctypes.byref(r), 1, ctypes.byref(n)) == \
+        B.BM_ERR_UNSUPPORTED

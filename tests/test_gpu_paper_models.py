@@ -1,4 +1,4 @@
-"""The paper's own validation (Sec. 5, Fig. 3) on the GPU: Models I and II with the
+"""The paper's own validation (Sec. 6, Fig. 3) on the GPU: Models I and II with the
 symmetric tent potential (eq. 2, L = 2) at D_G = 0, FP32 paths, 1024 particles,
 10^3 characteristic times, 10% of the run discarded, against the stationary
 velocities of eqs. (21)-(23) (eq. 21b with the sign the dynamics of eqs. 12-14

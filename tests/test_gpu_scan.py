@@ -7,6 +7,7 @@ launch shape; FP64 scan points are also compared with the oracle directly.
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
 import pytest
@@ -157,4 +158,48 @@ def test_autotune_sets_default():
     got = run_scan(pts)
     for w, g in zip(pts, got):
         assert stats_bytes(g) == stats_bytes(ensemble_stats(w))
+    B.bm_tune_set_default(pts[0].dyn, pts[0].pot, pts[0].noise, pts[0].prec, B.make_tune())
+
+
+def test_tune_cache_reused_by_a_second_process(tmp_path):
+    """The tuned shape is written to a JSON cache keyed by device and model family; a
+    second process loads it and gets the same shape without timing anything."""
+    import json
+    import subprocess
+    import sys
+
+    import torch
+    pts = mixed_points(W.F32)
+    mr = [W.to_c(w) for w in pts]
+    models, runs = [m for m, _ in mr], [r for _, r in mr]
+    nb = B.bm_scan_workspace_size(models, runs)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    res = torch.empty(len(pts) * B.STATS_BYTES, dtype=torch.uint8, device="cuda")
+    cache = str(tmp_path / "tune.json")
+    stream = torch.cuda.current_stream().cuda_stream
+    t, ms = B.autotune_cached(models, runs, 400, ws.data_ptr(), nb, res.data_ptr(), stream, cache)
+    assert ms is not None and ms > 0                               # timed: no cache yet
+    doc = json.load(open(cache))
+    key = dict(dyn=pts[0].dyn, pot=pts[0].pot, noise=pts[0].noise, prec=pts[0].prec)
+    mine = [e for e in doc["entries"] if all(e[k] == v for k, v in key.items())]
+    assert len(mine) == 1 and mine[0]["arch"].startswith("gfx950")
+    assert (mine[0]["paths_per_lane"], mine[0]["block"]) == (t.paths_per_lane, t.block)
+    code = (
+        "import sys, json, time; sys.path.insert(0, %r)\n"
+        "from paper_1409_4923_amd import bmotor as B, workloads as W\n"
+        "import test_gpu_scan as T\n"
+        "pts = T.mixed_points(W.F32)\n"
+        "mr = [W.to_c(w) for w in pts]\n"
+        "assert B.bm_tune_lookup(pts[0].dyn, pts[0].pot, pts[0].noise, pts[0].prec) is None\n"
+        "t0 = time.perf_counter()\n"
+        "t, ms = B.autotune_cached([m for m, _ in mr], [r for _, r in mr], 400, 0, 0, 0, 0, %r)\n"
+        "print(json.dumps([t.paths_per_lane, t.block, t.groups_per_cu, ms, time.perf_counter() - t0]))\n"
+    ) % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))), cache)
+    env = dict(os.environ)
+    env["PYTHONPATH"] = os.path.dirname(os.path.abspath(__file__)) + os.pathsep + env.get("PYTHONPATH", "")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, env=env)
+    assert out.returncode == 0, out.stderr[-2000:]
+    ppl, block, gpc, ms2, secs = json.loads(out.stdout.strip().splitlines()[-1])
+    assert (ppl, block, gpc) == (t.paths_per_lane, t.block, t.groups_per_cu)
+    assert ms2 is None                                             # taken from the cache, no timing
     B.bm_tune_set_default(pts[0].dyn, pts[0].pot, pts[0].noise, pts[0].prec, B.make_tune())
