@@ -132,6 +132,11 @@ def kernel_sources_sha256():
 ORACLE_SUBSET = 4096
 
 
+def _c2_jump_grid():
+    from paper_1409_4923_amd import workloads as W
+    return W.C2.with_(name="inertial-poisson-jump-grid-f32-2^20", noise=W.GAUSS | W.POISSON | W.JUMP_GRID)
+
+
 def host_threads() -> int:
     """Host threads this process may run on (its CPU affinity set)."""
     try:
@@ -446,14 +451,39 @@ def surrogate_leg(args):
     thr, tol = 0.005, 0.01
     xl = W.surrogate_queries(args.labels, seed=101)
     lab = S.monte_carlo(xl, args.label_paths, args.label_periods, seed=1, first_point=0)
+    t_label = lab.seconds
+    yl = lab.mean
     print("surrogate: %d labels in %.1f s" % (args.labels, lab.seconds), file=sys.stderr, flush=True)
     sur = B.Surrogate(5, seed=7)
     t0 = time.perf_counter()
-    hist = S.train(sur, xl, lab.mean, epochs=args.epochs, batch=1024, lr=2e-3, seed=3)
+    hist = S.train(sur, xl, yl, epochs=args.epochs, batch=1024, lr=2e-3, seed=3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     print("surrogate: trained in %.1f s, loss %.4g -> %.4g" % (t_train, hist[0], hist[-1]), file=sys.stderr,
           flush=True)
+    # active learning: label the candidates the ensemble disagrees on most, retrain on all
+    rounds = []
+    for rd in range(args.active_rounds):
+        xc = W.surrogate_queries(args.active_candidates, seed=500 + rd)
+        t0 = time.perf_counter()
+        pick = S.uncertain_points(sur, xc, args.active_labels, thr)
+        t_pick = time.perf_counter() - t0
+        if len(pick) == 0:
+            break
+        lab_a = S.monte_carlo(xc[pick], args.label_paths, args.label_periods, seed=1,
+                              first_point=(1 << 22) + rd * args.active_candidates)
+        xl = np.concatenate([xl, xc[pick]])
+        yl = np.concatenate([yl, lab_a.mean])
+        t0 = time.perf_counter()
+        h = S.train(sur, xl, yl, epochs=args.active_epochs, batch=1024, lr=1e-3, seed=4 + rd)
+        torch.cuda.synchronize()
+        t_tr = time.perf_counter() - t0
+        t_label += lab_a.seconds + t_pick
+        t_train += t_tr
+        rounds.append({"labels_added": int(len(pick)), "label_seconds": lab_a.seconds, "train_seconds": t_tr,
+                       "train_loss": [h[0], h[-1]]})
+        print("surrogate: active round %d: %d labels (%.1f s), retrained in %.1f s" %
+              (rd, len(pick), lab_a.seconds, t_tr), file=sys.stderr, flush=True)
     xh = W.surrogate_queries(args.heldout, seed=202)
     truth = S.monte_carlo(xh, args.truth_paths, args.label_periods, seed=2, first_point=1 << 24)
     rate = truth.path_steps / truth.seconds                              # MC path-steps/s on this workload
@@ -484,15 +514,16 @@ def surrogate_leg(args):
     delivered = n_q * ((1.0 - f) * good + f)
     t_sur = t_query + f * n_q * fb_cost
     sur_rate = delivered / t_sur
-    sur_rate_amortised = delivered / (t_sur + lab.seconds + t_train)
+    sur_rate_amortised = delivered / (t_sur + t_label + t_train)
     mc_rate = 1.0 / mc_cost
     # Plain MC that does not know sigma_i in advance: one path count for every point,
     # the largest the held-out points need; the fallback then pays the same.
     fixed_cost = float(np.max(need)) * n_steps / rate
     sur_rate_fixed = delivered / (t_query + f * n_q * fixed_cost)
     flops = n_q * 5 * 2 * (5 * 256 + 2 * 256 * 256 + 256)
-    return {"labels": args.labels, "label_budget": [args.label_paths, args.label_periods],
-            "label_seconds": lab.seconds, "train_seconds": t_train, "epochs": args.epochs,
+    return {"labels": int(len(xl)), "labels_uniform": args.labels, "active_rounds": rounds,
+            "label_budget": [args.label_paths, args.label_periods],
+            "label_seconds": t_label, "train_seconds": t_train, "epochs": args.epochs,
             "train_loss": [hist[0], hist[-1]],
             "heldout": args.heldout, "truth_paths": args.truth_paths, "truth_se_median": float(np.median(truth.se)),
             "queries": n_q, "threshold": thr, "query_seconds": t_query,
@@ -514,24 +545,31 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c2jump", "c3"],
+                    help="main workload: c2 = inertial Poisson (fixed grid), c2jump = the same on the "
+                         "jump-adapted grid, c3 = overdamped dichotomous, c1 = inertial Gaussian FP64")
     ap.add_argument("--ppl", type=int, default=0, help="paths per lane (0: library default)")
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="c3,c2jump,scan,scheme,infer,surrogate",
                     help="extra legs: c3, c2jump, scan, scheme, infer, surrogate (or none)")
-    ap.add_argument("--labels", type=int, default=200_000)
+    ap.add_argument("--labels", type=int, default=100_000, help="uniform labels before active learning")
+    ap.add_argument("--active-rounds", type=int, default=1)
+    ap.add_argument("--active-labels", type=int, default=100_000, help="labels added per active round")
+    ap.add_argument("--active-candidates", type=int, default=1_000_000)
+    ap.add_argument("--active-epochs", type=int, default=100)
     ap.add_argument("--label-paths", type=int, default=256)
     ap.add_argument("--label-periods", type=int, default=100)
-    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--epochs", type=int, default=150)
     ap.add_argument("--heldout", type=int, default=10_000)
     ap.add_argument("--truth-paths", type=int, default=4096)
     ap.add_argument("--queries", type=int, default=1_000_000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (for scaling HBM counters) and exit")
     ap.add_argument("--calibrate-valu", action="store_true",
-                    help="only measure the device's vector-ALU issue rate (FMA chains; FMA + compare + select) "
+                    help="only measure the device's vector-ALU issue rate (FMA chains; FMA + compare + select; "
+                         "FMA + exp2) "
                          "against the roofline peak and exit")
     args = ap.parse_args()
     if args.calibrate_valu:
@@ -541,7 +579,7 @@ def main():
         out = torch.empty(n, dtype=torch.float32, device="cuda")
         stream = torch.cuda.current_stream().cuda_stream
         rec = {"peak_lane_ops_per_s": VALU_LANE_OPS_PEAK}
-        for mix, name in ((0, "fma"), (1, "fma_cmp_select")):
+        for mix, name in ((0, "fma"), (1, "fma_cmp_select"), (2, "fma_exp2")):
             r = PR.valu_probe(mix, 20000, out.data_ptr(), n, stream)
             rec[name] = {"lane_ops_per_s": r, "frac_of_peak": r / VALU_LANE_OPS_PEAK}
         print(json.dumps({"valu_probe": rec}), flush=True)
@@ -565,7 +603,8 @@ def main():
     from paper_1409_4923_amd import bmotor as B
     from paper_1409_4923_amd import workloads as W
 
-    w = {"c1": W.C1, "c2": W.C2, "c3": W.C3}[args.config]
+    C2_JUMP_GRID = _c2_jump_grid()
+    w = {"c1": W.C1, "c2": W.C2, "c2jump": C2_JUMP_GRID, "c3": W.C3}[args.config]
     torch.cuda.set_device(torch.device("cuda:0"))
     tune = B.make_tune(args.ppl, args.block) if args.ppl else None
     wall, int_s, st, vp = time_ensemble(w, args.steps, args.warmup, tune)
@@ -619,10 +658,8 @@ def main():
     legs = [l for l in args.legs.split(",") if l and l != "none"]
     if "c3" in legs and w.name != W.C3.name:
         rec["c3"] = ensemble_leg(W.C3, 2, 1, threads, not args.no_cpu_baseline)
-    if "c2jump" in legs:
-        rec["c2_jump_adapted_grid"] = ensemble_leg(W.C2.with_(name="inertial-poisson-jump-grid-f32-2^20",
-                                                              noise=W.GAUSS | W.POISSON | W.JUMP_GRID),
-                                                   2, 1, threads, not args.no_cpu_baseline)
+    if "c2jump" in legs and w.name != C2_JUMP_GRID.name:
+        rec["c2_jump_adapted_grid"] = ensemble_leg(C2_JUMP_GRID, 2, 1, threads, not args.no_cpu_baseline)
     if "scan" in legs:
         rec["scan"] = scan_leg(args)
     if "scheme" in legs:

@@ -233,8 +233,8 @@ typedef struct bm_path {
     int64_t periods;         /* w: periods folded away; unwrapped position = periods L + x */
     double x;                /* folded position (within a couple of periods of [0, L))  */
     double v;                /* velocity (inertial; 0 for overdamped paths)             */
-    int64_t periods_window;  /* w and x at the window start t_i of eq. (31)             */
-    double x_window;
+    int64_t periods_window;  /* w and x at the window start t_i of eq. (31); 0 in      */
+    double x_window;         /* records read before the window start                    */
     double kick_frac;        /* jump-adapted grid: fraction of its step at which the
                                 next kick falls (0 otherwise)                          */
     int64_t noise[5];        /* Poisson countdown, Poisson kicks so far, dichotomous

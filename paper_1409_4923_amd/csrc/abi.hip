@@ -317,6 +317,7 @@ PointConst point_const(const bm_model *m, const bm_run *r, const void *d_tab)
         k.tol0_mua = (float)(2e-6 / k.mua_dt + 1e-6);
         k.tol0_mub = (float)(2e-6 / k.mub_dt + 1e-6);
     }
+    k.inv_spp = (float)(1.0 / (double)k.spp);
     k.drive_a = r->steps_per_period ? m->drive_amp : 0.0;
     k.drive_c = forcing_constant(m);
     k.x0_lo = r->x0_lo; k.x0_w = r->x0_hi - r->x0_lo;
@@ -441,7 +442,9 @@ extern "C" int bm_ensemble_set_tune(bm_ensemble *e, const bm_tune *t)
 {
     if (!e) return fail(BM_ERR_INVALID_ARG, "NULL handle");
     const bm_tune use = t ? *t : default_tune(e->model.dyn, e->model.pot, e->model.noise, e->run.prec);
-    int rc = check_tune(&use, e->model.noise, e->run.prec);
+    // the step-control kernel draws its jumps inline: no LDS queues to fit
+    const uint32_t queued = step_control(&e->run) ? (e->model.noise & BM_NOISE_GAUSS) : e->model.noise;
+    int rc = check_tune(&use, queued, e->run.prec);
     if (rc) return rc;
     if (t && step_control(&e->run) && use.paths_per_lane != 1)
         return fail(BM_ERR_UNSUPPORTED, "step control runs one path per lane");
@@ -554,12 +557,13 @@ extern "C" int bm_read_paths(bm_ensemble *e, uint64_t first, uint64_t count, dou
     if (rc) return rc;
     if ((uintptr_t)d_state & 7u) return fail(BM_ERR_INVALID_ARG, "d_state must be 8-byte aligned");
     if (count == 0) return ok();
-    const int with_vp = e->n_done > e->run.window_start ? 1 : 0;
+    const bool with_vp = e->n_done > e->run.window_start;
+    const int flags = (with_vp ? READ_VP : 0) | (e->n_done >= e->run.window_start ? READ_SNAP : 0);
     if (with_vp) set_window(e, k);
     const int pot = (int)e->model.pot;
     hipError_t he = e->run.prec == BM_F32
-                         ? launch_read_f32(pot, k, d_x, d_v, d_noise, d_vp, with_vp, d_state, e->stream)
-                         : launch_read_f64(pot, k, d_x, d_v, d_noise, d_vp, with_vp, d_state, e->stream);
+                         ? launch_read_f32(pot, k, d_x, d_v, d_noise, d_vp, flags, d_state, e->stream)
+                         : launch_read_f64(pot, k, d_x, d_v, d_noise, d_vp, flags, d_state, e->stream);
     if (he != hipSuccess) return hip_fail(he, "export kernel launch");
     return ok();
 }

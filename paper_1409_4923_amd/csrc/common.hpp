@@ -122,6 +122,7 @@ struct PointConst {
     float c_lam, c_mua, c_mub;   // ln 2 / (rate dt)
     float tol0_lam, tol0_mua, tol0_mub, tol1;
     float zeta_ln2;              // -zeta ln 2: z = zeta E = log2(1 - phi) * zeta_ln2
+    float inv_spp;               // 1 / spp (the drive phase inside a step, FP32 paths)
 };
 
 // ---------------------------------------------------------------------------

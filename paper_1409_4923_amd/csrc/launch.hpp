@@ -28,10 +28,13 @@ hipError_t launch_velocity_f32(int pot, const KArgs &a, hipStream_t s);
 hipError_t launch_velocity_f64(int pot, const KArgs &a, hipStream_t s);
 hipError_t launch_density_f32(int pot, const KArgs &a, uint32_t n_bins, unsigned long long *hist, hipStream_t s);
 hipError_t launch_density_f64(int pot, const KArgs &a, uint32_t n_bins, unsigned long long *hist, hipStream_t s);
+// flags of the export: READ_VP the per-path velocity exists (steps done > window
+// start), READ_SNAP the window snapshot exists (steps done >= window start)
+constexpr int READ_VP = 1, READ_SNAP = 2;
 hipError_t launch_read_f32(int pot, const KArgs &a, double *x, double *v, int64_t *nz, double *vp,
-                           int with_vp, bm_path *st, hipStream_t s);
+                           int flags, bm_path *st, hipStream_t s);
 hipError_t launch_read_f64(int pot, const KArgs &a, double *x, double *v, int64_t *nz, double *vp,
-                           int with_vp, bm_path *st, hipStream_t s);
+                           int flags, bm_path *st, hipStream_t s);
 hipError_t launch_write_f32(int pot, const KArgs &a, const bm_path *st, uint32_t snap, hipStream_t s);
 hipError_t launch_write_f64(int pot, const KArgs &a, const bm_path *st, uint32_t snap, hipStream_t s);
 

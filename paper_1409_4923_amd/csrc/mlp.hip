@@ -93,16 +93,16 @@ __global__ void k_loss_final(const float *partial, int nblk, int B, float *loss)
     loss[m] = s / (float)B;
 }
 
-// Gradients that are column sums over the batch rather than GEMMs: the biases
-// (db = sum_b dz[b][:]), the 1-wide output layer (dW4 = sum_b dy[b] a3[b][:],
-// db4 = sum_b dy[b]) and the 5-wide input layer (dW1[o][j] = sum_b dz1[b][o] u[b][j],
-// db1 = sum_b dz1[b][:]).  Pass 1: grid (n_chunks, members), lane = column o, each
-// block sums one chunk of consecutive rows; pass 2 adds the chunks in order, so the
-// result does not depend on the launch.
-enum { RED_BIAS = 0, RED_L4 = 1, RED_L1 = 2 };
+// Gradients that are column sums over the batch rather than GEMMs: the 1-wide
+// output layer (dW4 = sum_b dy[b] a3[b][:], db4 = sum_b dy[b]) and the 5-wide input
+// layer (dW1[o][j] = sum_b dz1[b][o] u[b][j], db1 = sum_b dz1[b][:]).  (The biases of
+// the 256 x 256 layers come with their weight-gradient GEMM.)  Pass 1: grid
+// (n_chunks, members), lane = column o, each block sums one chunk of consecutive
+// rows; pass 2 adds the chunks in order, so the result does not depend on the launch.
+enum { RED_L4 = 1, RED_L1 = 2 };
 
 template <int KIND>
-struct RedWidth { static constexpr int value = KIND == RED_BIAS ? 1 : KIND == RED_L4 ? 2 : IN + 1; };
+struct RedWidth { static constexpr int value = KIND == RED_L4 ? 2 : IN + 1; };
 
 constexpr int RED_MAX_CHUNKS = 64;
 
@@ -118,11 +118,10 @@ __global__ void __launch_bounds__(256) k_colsum(const bf16_t *dz, const float *d
 #pragma unroll
     for (int q = 0; q < NV; ++q) s[q] = 0.0f;
     const uint64_t row0 = (uint64_t)m * B + (uint64_t)c * rows;
+#pragma unroll 8
     for (int r = 0; r < rows; ++r) {
         const uint64_t row = row0 + r;
-        if constexpr (KIND == RED_BIAS) {
-            s[0] += bf2f(dz[row * H + o]);
-        } else if constexpr (KIND == RED_L4) {
+        if constexpr (KIND == RED_L4) {
             const float d = dy[row];
             s[0] = fmaf(d, bf2f(a3[row * H + o]), s[0]);
             s[1] += d;
@@ -138,21 +137,21 @@ __global__ void __launch_bounds__(256) k_colsum(const bf16_t *dz, const float *d
 }
 
 template <int KIND>
-__global__ void __launch_bounds__(256) k_colsum_final(const float *part, int nchunk, float *grad, int off)
+__global__ void __launch_bounds__(256) k_colsum_final(const float *part, int nchunk, float *grad)
 {
     constexpr int NV = RedWidth<KIND>::value;
     const int m = blockIdx.x, o = threadIdx.x;
     float s[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) s[q] = 0.0f;
+    // the chunks in order; unrolled so that the loads of several chunks are in flight
+#pragma unroll 8
     for (int c = 0; c < nchunk; ++c) {
 #pragma unroll
         for (int q = 0; q < NV; ++q) s[q] += part[(((uint64_t)m * nchunk + c) * NV + q) * H + o];
     }
     float *g = grad + (uint64_t)m * NPARAM;
-    if constexpr (KIND == RED_BIAS) {
-        g[off + o] = s[0];
-    } else if constexpr (KIND == RED_L4) {
+    if constexpr (KIND == RED_L4) {
         g[OFF_W4 + o] = s[0];
         if (o == 0) g[OFF_B4] = s[1];
     } else {
@@ -164,12 +163,32 @@ __global__ void __launch_bounds__(256) k_colsum_final(const float *part, int nch
 
 template <int KIND>
 hipError_t colsum(uint32_t nm, int B, const bf16_t *dz, const float *dy, const bf16_t *a3, const float *u,
-                  float *part, float *grad, int off, hipStream_t s)
+                  float *part, float *grad, hipStream_t s)
 {
     const int rows = red_rows(B), nchunk = B / rows;
     hipLaunchKernelGGL(k_colsum<KIND>, dim3(nchunk, nm), dim3(256), 0, s, dz, dy, a3, u, B, rows, part);
-    hipLaunchKernelGGL(k_colsum_final<KIND>, dim3(nm), dim3(256), 0, s, (const float *)part, nchunk, grad, off);
+    hipLaunchKernelGGL(k_colsum_final<KIND>, dim3(nm), dim3(256), 0, s, (const float *)part, nchunk, grad);
     return hipGetLastError();
+}
+
+// Weight and bias gradients of a 256 x 256 layer from the ks split-K partials of
+// the weight-gradient GEMM, each element's partials added in order; grid
+// (H * H / 256 + 1, members): the last block of a member adds the bias partials.
+__global__ void __launch_bounds__(256) k_wgrad_sum(const float *wpart, const float *bpart, int ks, int nm,
+                                                   float *grad, int woff, int boff)
+{
+    const int m = blockIdx.y, t = threadIdx.x;
+    constexpr int NB = H * H / 256;
+    float *g = grad + (uint64_t)m * NPARAM;
+    float s = 0.0f;
+    if ((int)blockIdx.x < NB) {
+        const uint64_t e = (uint64_t)blockIdx.x * 256 + t;
+        for (int kc = 0; kc < ks; ++kc) s += wpart[((uint64_t)kc * nm + m) * (H * H) + e];
+        g[woff + e] = s;
+    } else {
+        for (int kc = 0; kc < ks; ++kc) s += bpart[((uint64_t)kc * nm + m) * H + t];
+        g[boff + t] = s;
+    }
 }
 
 // dz3 = dy W4 gelu'(z3), grid (B, members), lane = column.
@@ -304,8 +323,18 @@ __global__ void __launch_bounds__(256) k_compact(const float *stdv, uint64_t B, 
 size_t up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct MlpLayout {
-    size_t u, z1, z2, z3, a1, a2, a3, y, dy, dz1, dz2, dz3, part, red, mean, stdv, blk, total;
+    size_t u, z1, z2, z3, a1, a2, a3, y, dy, dz1, dz2, dz3, part, red, wpart, bpart, mean, stdv, blk, total;
 };
+
+// Split of the batch (the K of the weight-gradient GEMMs) over work-groups: the
+// largest power of two <= min(WG_MAX_SPLIT, B / 256) with B / ksplit a multiple of 32.
+constexpr int WG_MAX_SPLIT = 8;
+int wgrad_split(int B)
+{
+    int ks = 1;
+    while (2 * ks <= WG_MAX_SPLIT && 2 * ks * 256 <= B && B % (2 * ks * TK) == 0) ks *= 2;
+    return ks;
+}
 
 MlpLayout mlp_layout(uint32_t nm, uint64_t batch, bool training)
 {
@@ -330,6 +359,8 @@ MlpLayout mlp_layout(uint32_t nm, uint64_t batch, bool training)
         L.dz3 = take(nm * R * H * 2);
         L.part = take(nm * ((R + 255) / 256) * 4);
         L.red = take((size_t)nm * RED_MAX_CHUNKS * (IN + 1) * H * 4);
+        L.wpart = take((size_t)WG_MAX_SPLIT * nm * H * H * 4);
+        L.bpart = take((size_t)WG_MAX_SPLIT * nm * H * 4);
     } else {
         L.blk = take(((batch + 255) / 256) * 4 + 4);
     }
@@ -351,11 +382,18 @@ int check_ws(const MlpLayout &L, void *d_ws, size_t ws_bytes)
     return BM_OK;
 }
 
+// k tiles of 128 when every work-group's k range allows (K = 256 layers, 256-row
+// splits of the batch), else of 32.
 template <int EPI, bool TA, bool TB>
 hipError_t gemm(const GemmArgs &g, int members, hipStream_t s)
 {
-    const dim3 grid((uint32_t)(g.N / TN), (uint32_t)((g.M + TM - 1) / TM), (uint32_t)members);
-    hipLaunchKernelGGL((k_gemm<EPI, TA, TB>), grid, dim3(256), 0, s, g);
+    const int ks = g.ksplit > 1 ? g.ksplit : 1;
+    const int krange = ks > 1 ? g.kchunk : g.K;
+    const dim3 grid((uint32_t)(g.N / TN), (uint32_t)((g.M + TM - 1) / TM), (uint32_t)(members * ks));
+    if (krange % 128 == 0)
+        hipLaunchKernelGGL((k_gemm<EPI, TA, TB, 128>), grid, dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((k_gemm<EPI, TA, TB, TK>), grid, dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
@@ -656,7 +694,7 @@ extern "C" int bm_mlp_backward(uint32_t n_members, const float *d_params, const 
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
-        e = colsum<RED_L4>(nm, B, nullptr, dy, a3, nullptr, red, d_grad, 0, s);
+        e = colsum<RED_L4>(nm, B, nullptr, dy, a3, nullptr, red, d_grad, s);
         if (e == hipSuccess) {
             hipLaunchKernelGGL(k_l4_bwd_dz, dim3(B, nm), dim3(256), 0, s, dy, wbf, z3, B, dz3);
             e = hipGetLastError();
@@ -668,15 +706,23 @@ extern "C" int bm_mlp_backward(uint32_t n_members, const float *d_params, const 
     const bf16_t *aprev[2] = {a2, a1};
     const float *zprev[2] = {z2, z1};
     const int woff[2] = {OFF_W3, OFF_W2}, boff[2] = {OFF_B3, OFF_B2}, bwoff[2] = {BOFF_W3, BOFF_W2};
+    const int ks = wgrad_split(B);
+    float *wpart = (float *)(ws + L.wpart), *bpart = (float *)(ws + L.bpart);
     for (int l = 0; l < 2 && e == hipSuccess; ++l) {
+        // dW = dz^T a_prev split over the batch, with the bias gradient (the row sums
+        // of dz^T) from the same staged tiles; then the partials added in order
         GemmArgs g = gemm_args();
         g.A = dzs[l]; g.a_mstride = (uint64_t)B * H; g.lda = H;          // (m = out, k = row): dz[k][m]
         g.B = aprev[l]; g.b_mstride = (uint64_t)B * H; g.ldb = H;        // (k = row, n = in): a[k][n]
         g.M = H; g.N = H; g.K = B;
-        g.out_f = d_grad + woff[l]; g.out_mstride = NPARAM; g.ldc = H;
+        g.out_f = wpart; g.out_mstride = (uint64_t)H * H; g.ldc = H;
+        g.ksplit = ks; g.kchunk = B / ks; g.out_kstride = (uint64_t)nm * H * H;
+        g.bias_part = bpart; g.bias_kstride = (uint64_t)nm * H;
         e = gemm<EPI_STORE, true, true>(g, (int)nm, s);
         if (e != hipSuccess) break;
-        e = colsum<RED_BIAS>(nm, B, dzs[l], nullptr, nullptr, nullptr, red, d_grad, boff[l], s);
+        hipLaunchKernelGGL(k_wgrad_sum, dim3(H * H / 256 + 1, nm), dim3(256), 0, s, (const float *)wpart,
+                           (const float *)bpart, ks, (int)nm, d_grad, woff[l], boff[l]);
+        e = hipGetLastError();
         if (e != hipSuccess) break;
         GemmArgs d = gemm_args();
         d.A = dzs[l]; d.a_mstride = (uint64_t)B * H; d.lda = H;          // (m = row, k = out)
@@ -687,7 +733,7 @@ extern "C" int bm_mlp_backward(uint32_t n_members, const float *d_params, const 
         e = gemm<EPI_DGRAD, false, true>(d, (int)nm, s);
     }
     if (e == hipSuccess) {
-        e = colsum<RED_L1>(nm, B, dz1, nullptr, nullptr, u, red, d_grad, 0, s);
+        e = colsum<RED_L1>(nm, B, dz1, nullptr, nullptr, u, red, d_grad, s);
     }
     return e == hipSuccess ? ok() : hip_fail(e, "bm_mlp_backward");
 }
@@ -771,4 +817,3 @@ extern "C" int bm_surrogate_query(uint32_t n_members, const float *d_params, con
                                        (uint32_t *)(ws + L.blk), (hipStream_t)stream);
     return e == hipSuccess ? ok() : hip_fail(e, "bm_surrogate_query");
 }
-

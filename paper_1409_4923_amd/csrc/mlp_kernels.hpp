@@ -86,8 +86,8 @@ __device__ __forceinline__ void normalise(const float *x, float u[IN])
 // (blockIdx.z selects the member through the *_mstride element strides).
 //   A: TA = false -> element (m, k) at A[m * lda + k];  TA = true -> A[k * lda + m]
 //   B: TB = false -> element (k, n) at B[n * ldb + k];  TB = true -> B[k * ldb + n]
-// Tiles 64 x 64 x 32, 256 lanes = 4 waves, each wave 32 x 32 = 2 x 2 MFMA tiles.
-// Requirements (checked on the host): N % 64 == 0, K % 32 == 0, 16-byte aligned
+// Tiles 64 x 64 x TKT, 256 lanes = 4 waves, each wave 32 x 32 = 2 x 2 MFMA tiles.
+// Requirements (checked on the host): N % 64 == 0, K % TKT == 0, 16-byte aligned
 // rows (lda, ldb multiples of 8).  M is arbitrary (rows >= M read as 0, not stored).
 // ---------------------------------------------------------------------------
 enum Epi : int {
@@ -104,17 +104,35 @@ struct GemmArgs {
     const float *zin; uint64_t zin_mstride; int ldz;    // EPI_DGRAD: z (FP32, [M][ldz])
     float *zout; uint64_t zout_mstride;                 // EPI_FWD: optional z out ([M][ldc])
     bf16_t *out_bf; float *out_f; uint64_t out_mstride; int ldc;
+    // split K (EPI_STORE): blockIdx.z = member * ksplit + kc covers k in
+    // [kc kchunk, (kc + 1) kchunk) and stores its partial at out_f + kc out_kstride;
+    // with bias_part, the work-groups of the first column tile also store the row
+    // sums of their A range, sum_k A(m, k), at bias_part[kc bias_kstride + member H + m]
+    // (TA only).  ksplit 0 or 1: the whole K in one work-group.
+    int ksplit, kchunk;
+    uint64_t out_kstride;
+    float *bias_part; uint64_t bias_kstride;
 };
 
-constexpr int TM = 64, TN = 64, TK = 32, LDSK = TK + 8;   // +8 bf16 pad per row
+constexpr int TM = 64, TN = 64, TK = 32;
 
-template <int EPI, bool TA, bool TB>
+// TKT: k extent of the tiles staged per barrier (a multiple of 32 dividing K, or the
+// split's kchunk): 32 keeps 10 KiB of LDS per work-group; 128 halves the barriers
+// and global-load round trips four times over for the K = 256 layers.
+template <int EPI, bool TA, bool TB, int TKT = TK>
 __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
 {
-    __shared__ __align__(16) bf16_t sA[TM * LDSK];
-    __shared__ __align__(16) bf16_t sB[TN * LDSK];
+    constexpr int LK = TKT + 8;          // padded row of a staged tile (bf16)
+    constexpr int KS = TKT / 32;         // 32-wide k slices per staged tile
+    __shared__ __align__(16) bf16_t sA[TM * LK];
+    __shared__ __align__(16) bf16_t sB[TN * LK];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN, mem = blockIdx.z;
+    const int ks = g.ksplit > 1 ? g.ksplit : 1;
+    const int kc = (int)blockIdx.z % ks, mem = (int)blockIdx.z / ks;
+    const int kbeg = ks > 1 ? kc * g.kchunk : 0, kend = ks > 1 ? kbeg + g.kchunk : g.K;
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+    const bool rowsum = TA && EPI == EPI_STORE && g.bias_part != nullptr && blockIdx.x == 0;
+    float bsum = 0.0f;
     const bf16_t *A = g.A + g.a_mstride * mem;
     const bf16_t *B = g.B + g.b_mstride * mem;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -124,47 +142,79 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < g.K; k0 += TK) {
-        // ---- stage A (64 x 32) ----
-        if (!TA) {
-            const int r = t >> 2, kc = (t & 3) * 8;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (m0 + r < g.M) v = *reinterpret_cast<const uint4 *>(A + (uint64_t)(m0 + r) * g.lda + k0 + kc);
-            *reinterpret_cast<uint4 *>(&sA[r * LDSK + kc]) = v;
-        } else {
-            const int kk = t >> 3, mc = (t & 7) * 8;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (m0 + mc < g.M) v = *reinterpret_cast<const uint4 *>(A + (uint64_t)(k0 + kk) * g.lda + m0 + mc);
-            const bf16_t *e = reinterpret_cast<const bf16_t *>(&v);
+    for (int k0 = kbeg; k0 < kend; k0 += TKT) {
+        // ---- stage A (64 x TKT) and B (TKT x 64, stored n-major), 32 k at a time ----
+        uint4 va[KS], vb[KS];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) sA[(mc + i) * LDSK + kk] = e[i];
+        for (int sl = 0; sl < KS; ++sl) {
+            const int kb = k0 + 32 * sl;
+            va[sl] = make_uint4(0u, 0u, 0u, 0u);
+            if (!TA) {
+                const int r = t >> 2, kq = (t & 3) * 8;
+                if (m0 + r < g.M) va[sl] = *reinterpret_cast<const uint4 *>(A + (uint64_t)(m0 + r) * g.lda + kb + kq);
+            } else {
+                const int kk = t >> 3, mc = (t & 7) * 8;
+                if (m0 + mc < g.M) va[sl] = *reinterpret_cast<const uint4 *>(A + (uint64_t)(kb + kk) * g.lda + m0 + mc);
+            }
+            if (!TB) {
+                const int c = t >> 2, kq = (t & 3) * 8;
+                vb[sl] = *reinterpret_cast<const uint4 *>(B + (uint64_t)(n0 + c) * g.ldb + kb + kq);
+            } else {
+                const int kk = t >> 3, nc = (t & 7) * 8;
+                vb[sl] = *reinterpret_cast<const uint4 *>(B + (uint64_t)(kb + kk) * g.ldb + n0 + nc);
+            }
         }
-        // ---- stage B (32 x 64) stored n-major ----
-        if (!TB) {
-            const int c = t >> 2, kc = (t & 3) * 8;
-            const uint4 v = *reinterpret_cast<const uint4 *>(B + (uint64_t)(n0 + c) * g.ldb + k0 + kc);
-            *reinterpret_cast<uint4 *>(&sB[c * LDSK + kc]) = v;
-        } else {
-            const int kk = t >> 3, nc = (t & 7) * 8;
-            const uint4 v = *reinterpret_cast<const uint4 *>(B + (uint64_t)(k0 + kk) * g.ldb + n0 + nc);
-            const bf16_t *e = reinterpret_cast<const bf16_t *>(&v);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) sB[(nc + i) * LDSK + kk] = e[i];
+        for (int sl = 0; sl < KS; ++sl) {
+            if (!TA) {
+                const int r = t >> 2, kq = (t & 3) * 8;
+                *reinterpret_cast<uint4 *>(&sA[r * LK + 32 * sl + kq]) = va[sl];
+            } else {
+                const int kk = t >> 3, mc = (t & 7) * 8;
+                const bf16_t *e = reinterpret_cast<const bf16_t *>(&va[sl]);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) sA[(mc + i) * LK + 32 * sl + kk] = e[i];
+            }
+            if (!TB) {
+                const int c = t >> 2, kq = (t & 3) * 8;
+                *reinterpret_cast<uint4 *>(&sB[c * LK + 32 * sl + kq]) = vb[sl];
+            } else {
+                const int kk = t >> 3, nc = (t & 7) * 8;
+                const bf16_t *e = reinterpret_cast<const bf16_t *>(&vb[sl]);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) sB[(nc + i) * LK + 32 * sl + kk] = e[i];
+            }
         }
         __syncthreads();
-        // ---- 2 x 2 MFMA 16x16x32 per wave: lane holds row/col lane%16, k 8*(lane/16).. ----
+        // ---- 2 x 2 MFMA 16x16x32 per wave and k slice: lane holds row/col lane%16,
+        //      k 8*(lane/16).. of the slice ----
         const int fr = lane & 15, fk = (lane >> 4) * 8;
-        bf16x8 af[2], bfr[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const bf16x8 *>(&sA[(wm + 16 * i + fr) * LDSK + fk]);
+        for (int sl = 0; sl < KS; ++sl) {
+            bf16x8 af[2], bfr[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) bfr[j] = *reinterpret_cast<const bf16x8 *>(&sB[(wn + 16 * j + fr) * LDSK + fk]);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
+                af[i] = *reinterpret_cast<const bf16x8 *>(&sA[(wm + 16 * i + fr) * LK + 32 * sl + fk]);
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+                bfr[j] = *reinterpret_cast<const bf16x8 *>(&sB[(wn + 16 * j + fr) * LK + 32 * sl + fk]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+        if (rowsum) {                    // row t/4 of the A tile, a quarter of its k
+#pragma unroll
+            for (int i = 0; i < TKT / 4; ++i) bsum += bf2f(sA[(t >> 2) * LK + (t & 3) * (TKT / 4) + i]);
+        }
         __syncthreads();
+    }
+    if (rowsum) {
+        bsum += __shfl_xor(bsum, 1, 64);
+        bsum += __shfl_xor(bsum, 2, 64);
+        if ((t & 3) == 0 && m0 + (t >> 2) < g.M)
+            g.bias_part[(uint64_t)kc * g.bias_kstride + (uint64_t)mem * H + m0 + (t >> 2)] = bsum;
     }
 
     // ---- epilogue: acc[i][j][e] is C[row 4*(lane/16)+e][col lane%16] of tile (i, j) ----
@@ -178,7 +228,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
                 const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + e;
                 if (m >= g.M) continue;
                 const float v = acc[i][j][e];
-                const uint64_t o = g.out_mstride * mem + (uint64_t)m * g.ldc + n;
+                const uint64_t o = g.out_kstride * kc + g.out_mstride * mem + (uint64_t)m * g.ldc + n;
                 if constexpr (EPI == EPI_FWD) {
                     const float z = v + g.bias[g.bias_mstride * mem + n];
                     if (g.zout) g.zout[g.zout_mstride * mem + (uint64_t)m * g.ldc + n] = z;

@@ -4,7 +4,10 @@
 // translation unit (paths_f32.hip, paths_f64.hip), which instantiate them.
 #pragma once
 
+#include <type_traits>
+
 #include "bmotor.h"
+#include "launch.hpp"
 #include "paths.hpp"
 #include "reduce.hpp"
 
@@ -59,7 +62,7 @@ template <typename R> struct JumpCursor {
     R zP;           // its amplitude
     const KickEntry<R> *pP;   // the queue entry after it
     uint32_t nD;    // offset of the next flip
-    uint32_t cD;    // element index of the next queue slot (FLIP_INLINE: drawn inline)
+    uint32_t cD;    // element index of the next queue slot
     // jump-adapted grid
     JGKick<R> g;    // next kick (g.off == JG_NONE: none left in the window)
     uint32_t gs;    // queue slot of g
@@ -67,7 +70,6 @@ template <typename R> struct JumpCursor {
     uint32_t poff;  // offset of the first kick not yet drawn
     double pth;     // its fraction of the step (FP64: kick times decide the integer state)
 };
-constexpr uint32_t FLIP_INLINE = 0xFFFFFFFFu;
 
 // Forcing at the time t_n + theta dt inside a step of drive phase k (jump-adapted
 // grid): a cos(2 pi (k + theta) / spp) + tilt - Poisson bias + potential offset.
@@ -75,7 +77,7 @@ constexpr uint32_t FLIP_INLINE = 0xFFFFFFFFu;
 template <typename R> __device__ __forceinline__ R drive_inside(const PointConst &a, uint32_t k, double th)
 {
     if constexpr (sizeof(R) == 4) {
-        const float turns = ((float)k + (float)th) / (float)a.spp;
+        const float turns = ((float)k + (float)th) * a.inv_spp;      // within 2 ulp of the quotient
         return (float)a.drive_a * __builtin_amdgcn_cosf(turns) + (float)a.drive_c;
     } else {
         constexpr double PI = 3.14159265358979323846;
@@ -142,39 +144,86 @@ __device__ __forceinline__ JGKick<R> jg_draw(const PointConst &a, uint32_t path,
     return e;
 }
 
-// Queue up to jg_cap<R>() kicks of one window (wave-uniform loop, as for the fixed grid);
-// kicks beyond a full queue are drawn at their steps.
+// The same draw out of line, for the rare step that holds more kicks than a queue
+// (arguments and results by value, so that the caller's state stays in registers).
+template <typename R> struct JGDrawn {
+    JGKick<R> e;
+    double th;
+    uint32_t kP, off;
+};
 template <typename R, int NOISE>
-__device__ __forceinline__ void jg_window(const PointConst &a, uint32_t path, uint32_t wlen, uint32_t &kP,
-                                          JumpCursor<R> &J, JGKick<R> *q, uint32_t qs)
+__device__ __noinline__ JGDrawn<R> jg_draw_inline(const PointConst a, uint32_t path, uint32_t kP, uint32_t off,
+                                                  double th)
 {
-    uint32_t slot = 0;
-    bool active = J.poff < wlen;
+    JGDrawn<R> d;
+    d.e = jg_draw<R, NOISE>(a, path, kP, off, th);
+    d.th = th;
+    d.kP = kP;
+    d.off = off;
+    return d;
+}
+
+// Fill the queue of one window (wave-uniform loop, as for the fixed grid) behind the
+// J.gn kicks carried over from the previous window, up to jg_cap<R>() kicks, with the
+// kicks that fall before the window's end.  Returns the number of leading steps of
+// the window whose kicks are all queued: wlen, or, when the queue is full, the offset
+// of the first kick it does not hold (J.poff).
+template <typename R, int NOISE>
+__device__ __forceinline__ uint32_t jg_window(const PointConst &a, uint32_t path, uint32_t wlen, uint32_t &kP,
+                                              JumpCursor<R> &J, JGKick<R> *q, uint32_t qs)
+{
+    uint32_t slot = J.gn;
+    bool active = J.poff < wlen && slot < jg_cap<R>();
     while (__any(active)) {
         if (active) {
-            if (slot < jg_cap<R>()) {
-                q[slot * qs] = jg_draw<R, NOISE>(a, path, kP, J.poff, J.pth);
-                ++slot;
-                active = J.poff < wlen;
-            } else {
-                active = false;
-            }
+            q[slot * qs] = jg_draw<R, NOISE>(a, path, kP, J.poff, J.pth);
+            ++slot;
+            active = J.poff < wlen && slot < jg_cap<R>();
         }
     }
     J.gn = slot;
     J.gs = 0;
     if (slot > 0) J.g = q[0];
     else J.g.off = JG_NONE;
+    return J.poff < wlen ? J.poff : wlen;
 }
 
-// Moves the cursor past the kick just applied.
-template <typename R, int NOISE>
+// At the end of a window of wlen steps: the kicks still queued (drawn for steps past
+// an early end) move to the front of the queue with their offsets rebased, and the
+// offset of the first kick not yet drawn is rebased too.  The kick draws stay in
+// their sequence, so nothing is drawn twice or given back.
+template <typename R>
+__device__ __forceinline__ void jg_carry(JumpCursor<R> &J, JGKick<R> *q, uint32_t qs, uint32_t wlen)
+{
+    const uint32_t left = J.gn - J.gs;                    // gs <= gn <= jg_cap (jg_advance)
+    for (uint32_t i = 0; i < jg_cap<R>() && __any(i < left); ++i) {
+        if (i < left) {
+            JGKick<R> e = q[(J.gs + i) * qs];               // source index >= destination
+            e.off -= wlen;
+            q[i * qs] = e;
+        }
+    }
+    J.gn = left;
+    J.gs = 0;
+    J.poff -= wlen;
+}
+
+// Moves the cursor past the kick just applied.  Within a window every kick before
+// its end is queued; only the single-step fallback (INL) draws past its queue.  The
+// cursor index stops at the queue's end (gs <= gn), also while kicks are drawn inline.
+template <typename R, int NOISE, bool INL>
 __device__ __forceinline__ void jg_advance(const PointConst &a, uint32_t path, uint32_t wlen, uint32_t &kP,
                                            JumpCursor<R> &J, const JGKick<R> *q, uint32_t qs)
 {
-    ++J.gs;
+    if (J.gs < J.gn) ++J.gs;                  // the kick applied was the queue's entry gs
     if (J.gs < J.gn) J.g = q[J.gs * qs];
-    else if (J.poff < wlen) J.g = jg_draw<R, NOISE>(a, path, kP, J.poff, J.pth);    // queue overflow
+    else if (INL && J.poff < wlen) {
+        const JGDrawn<R> d = jg_draw_inline<R, NOISE>(a, path, kP, J.poff, J.pth);
+        J.g = d.e;
+        J.pth = d.th;
+        J.poff = d.off;
+        kP = d.kP;
+    }
     else J.g.off = JG_NONE;
 }
 
@@ -185,7 +234,7 @@ __device__ __forceinline__ void jg_advance(const PointConst &a, uint32_t path, u
 // (one per further kick in the step, then the rest of the step).  The first piece
 // takes the step's own Gaussian increment scaled by sqrt(theta); a piece after
 // kick k takes the increment drawn for k.
-template <typename R, int DYN, int POT, int NOISE>
+template <typename R, int DYN, int POT, int NOISE, bool INL>
 __device__ __forceinline__ void jg_step(const PointConst &a, uint32_t path, Path<R> &s, JumpCursor<R> &J,
                                         const JGKick<R> *q, uint32_t qs, uint32_t wlen, uint32_t off,
                                         uint32_t kph, R dxi, R h, R hh, R ngam, R kp, R A0, R A1, R lev)
@@ -196,7 +245,17 @@ __device__ __forceinline__ void jg_step(const PointConst &a, uint32_t path, Path
         return;
     }
     R th1 = R(1), A_e = A1, dxi1 = dxi, z1 = R(0);
-    if (kick) {
+    if constexpr (sizeof(R) == 4) {
+        // FP32: the kick's values formed in every lane and selected (no divergent
+        // branch; the cosine and square root go to the transcendental unit)
+        const R thk = J.g.th;
+        const R A_k = drive_inside<R>(a, kph, (double)thk) + lev;
+        const R dxk = dxi * piece_sqrt(thk);
+        th1 = kick ? thk : R(1);
+        A_e = kick ? A_k : A1;
+        dxi1 = kick ? dxk : dxi;
+        z1 = kick ? J.g.z : R(0);
+    } else if (kick) {
         th1 = J.g.th;
         A_e = drive_inside<R>(a, kph, (double)th1) + lev;
         dxi1 = dxi * piece_sqrt(th1);
@@ -205,7 +264,7 @@ __device__ __forceinline__ void jg_step(const PointConst &a, uint32_t path, Path
     pc_step<DYN, POT, true, R>(s, th1 * h, th1 * hh, ngam, kp, dxi1, z1, A0, A_e);
     if (kick) {
         R from = th1, A_from = A_e, u = J.g.u;
-        jg_advance<R, NOISE>(a, path, wlen, s.kP, J, q, qs);
+        jg_advance<R, NOISE, INL>(a, path, wlen, s.kP, J, q, qs);
         // further kicks in this step (lambda dt <= 16 is enforced on the host; the
         // bound only guarantees that every lane leaves the loop)
         for (uint32_t it = 0; J.g.off == off && it < JG_MAX_KICKS; ++it) {
@@ -216,7 +275,7 @@ __device__ __forceinline__ void jg_step(const PointConst &a, uint32_t path, Path
             from = th;
             A_from = A_th;
             u = J.g.u;
-            jg_advance<R, NOISE>(a, path, wlen, s.kP, J, q, qs);
+            jg_advance<R, NOISE, INL>(a, path, wlen, s.kP, J, q, qs);
         }
         pc_step<DYN, POT, false, R>(s, (R(1) - from) * h, (R(1) - from) * hh, ngam, kp, u * piece_sqrt(R(1) - from),
                                     R(0), A_from, A1);
@@ -227,7 +286,7 @@ __device__ __forceinline__ void jg_step(const PointConst &a, uint32_t path, Path
 // step, Algorithm 1, and the Poisson kick due at this step, which Algorithm 3 adds
 // to the corrector's result.  `dxi` is the Algorithm 2 increment.  (Folding is
 // done by the caller.)
-template <typename R, int DYN, int POT, int NOISE>
+template <typename R, int DYN, int POT, int NOISE, bool INL = false>
 __device__ __forceinline__ void full_step(const PointConst &a, uint32_t path, Path<R> &s, JumpCursor<R> &J,
                                           const JGKick<R> *gq, const uint32_t *fq,
                                           uint32_t qs, uint32_t wlen, uint32_t off, uint32_t kph, R dxi, R h,
@@ -237,21 +296,10 @@ __device__ __forceinline__ void full_step(const PointConst &a, uint32_t path, Pa
     if constexpr ((NOISE & NZ_DICH) != 0) {
         if (J.nD == off) {                       // Algorithm 4: s <= 0 at this step
             s.d = 1 - s.d;
-            if constexpr ((NOISE & NZ_JGRID) == 0) {
-                // the window ends before a full queue's marker: every flip is queued
-                const uint32_t e = fq[J.cD];
-                J.cD += qs;
-                J.nD = e & ~INLINE_BIT;
-            } else if (J.cD != FLIP_INLINE) {
-                const uint32_t e = fq[J.cD];
-                J.cD += qs;
-                if (e & INLINE_BIT) J.cD = FLIP_INLINE;
-                J.nD = e & ~INLINE_BIT;
-            } else {
-                const uint32_t sn = flip_draw<R>(a, path, s.mD, s.d);
-                ++s.mD;
-                J.nD = off + 1u + sn;
-            }
+            // the window ends before a full queue's marker: every flip is queued
+            const uint32_t e = fq[J.cD];
+            J.cD += qs;
+            J.nD = e & ~INLINE_BIT;
         }
     }
     R lev = R(0);
@@ -261,7 +309,7 @@ __device__ __forceinline__ void full_step(const PointConst &a, uint32_t path, Pa
         A1 = A1 + lev;
     }
     if constexpr ((NOISE & NZ_JGRID) != 0) {
-        jg_step<R, DYN, POT, NOISE>(a, path, s, J, gq, qs, wlen, off, kph, dxi, h, hh, ngam, kp, A0, A1, lev);
+        jg_step<R, DYN, POT, NOISE, INL>(a, path, s, J, gq, qs, wlen, off, kph, dxi, h, hh, ngam, kp, A0, A1, lev);
     } else {
         pc_step<DYN, POT, false, R>(s, h, hh, ngam, kp, dxi, R(0), A0, A1);
     }
@@ -315,6 +363,14 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
 
     uint64_t n = n0;
     uint32_t k = (uint32_t)(n % a.spp);           // drive phase of step n
+    if constexpr ((NOISE & NZ_JGRID) != 0) {
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {           // next kick not yet drawn; empty queue
+            J[j].poff = (uint32_t)s[j].sP;
+            J[j].pth = s[j].thP;
+            J[j].gn = 0;
+        }
+    }
 
     while (n < n1) {
         const uint64_t wnext = ((n >> a.jw_log2) + 1u) << a.jw_log2;
@@ -325,9 +381,8 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
             if constexpr ((NOISE & NZ_JGRID) != 0) {
-                J[j].poff = (uint32_t)s[j].sP;
-                J[j].pth = s[j].thP;
-                jg_window<R, NOISE>(a, path[j], wlen, s[j].kP, J[j], gq + col(j), qs);
+                const uint32_t c = jg_window<R, NOISE>(a, path[j], wlen, s[j].kP, J[j], gq + col(j), qs);
+                cover = c < cover ? c : cover;
             }
             if constexpr (queued_kicks<NOISE>()) {
                 const uint32_t c = kick_window<R>(a, path[j], wlen, (uint32_t)s[j].sP, s[j].kP, kq + col(j), qs);
@@ -340,16 +395,20 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
             if constexpr ((NOISE & NZ_DICH) != 0) {
                 const uint32_t c = flip_window<R>(a, path[j], wlen, (uint32_t)s[j].sD, s[j].mD, s[j].d,
                                                   fq + col(j), qs);
-                if constexpr ((NOISE & NZ_JGRID) == 0) cover = c < cover ? c : cover;
+                cover = c < cover ? c : cover;
                 const uint32_t e = fq[col(j)];
                 J[j].nD = e & ~INLINE_BIT;
-                J[j].cD = (e & INLINE_BIT) ? FLIP_INLINE : qs;
+                J[j].cD = qs;
             }
         }
-        if constexpr (queued_kicks<NOISE>() || (NOISE & (NZ_DICH | NZ_JGRID)) == NZ_DICH) {
+        // A lane whose step holds more kicks than its queue (jump-adapted grid only):
+        // that one step runs alone, drawing the kicks past the queue at the step.
+        bool single = false;
+        if constexpr (queued_kicks<NOISE>() || (NOISE & (NZ_DICH | NZ_JGRID)) != 0) {
             // A full kick or flip queue ends the window for the wave at the first
-            // jump it does not hold (the minimum over the lanes, at least JCAP steps
-            // in), rounded down to a 16-step block boundary when one lies after n.
+            // jump it does not hold (the minimum over the lanes; on the fixed grid at
+            // least JCAP steps in), rounded down to a 16-step block boundary when one
+            // lies after n.
             if (__any(cover < wlen)) {
                 uint32_t wl = wlen;
                 for (;;) {
@@ -359,16 +418,24 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                     // that step counters and forcing-table reads stay wave-uniform
                     wl = __builtin_amdgcn_readfirstlane((uint32_t)__shfl(cover, __ffsll((long long)b) - 1));
                 }
+                if constexpr ((NOISE & NZ_JGRID) != 0) {
+                    if (wl == 0) {
+                        single = true;
+                        wl = 1;
+                    }
+                }
                 uint64_t we = n + wl;
-                if ((we & ~(uint64_t)15) > n) we &= ~(uint64_t)15;
+                if (!single && (we & ~(uint64_t)15) > n) we &= ~(uint64_t)15;
                 wend = we;
                 wlen = (uint32_t)(we - n);
             }
         }
         uint32_t off = 0;
 
-        // Generic single step (block-unaligned window heads and tails).
-        auto one_step = [&]() {
+        // Generic single step (block-unaligned window heads and tails); INL: the
+        // single step whose kicks overflow a queue.
+        auto one_step = [&](auto inl) {
+            constexpr bool INL = decltype(inl)::value;
             const R A0 = drive_at<R>(a, k);
             const R A1 = drive_at<R>(a, k + 1u);
 #pragma unroll
@@ -390,9 +457,9 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                     normal_pair(hi ? q.z : q.x, hi ? q.w : q.y, zc, zs);
                     dxi = g3 * ((n & 1u) ? zs : zc);
                 }
-                full_step<R, DYN, POT, NOISE>(a, path[j], s[j], J[j], gq + col(j), fq + col(j), qs,
-                                              wlen, off, k,
-                                              dxi, h, hh, ngam, kp, A0, A1, Fa, Fb);
+                full_step<R, DYN, POT, NOISE, INL>(a, path[j], s[j], J[j], gq + col(j), fq + col(j), qs,
+                                                   wlen, off, k,
+                                                   dxi, h, hh, ngam, kp, A0, A1, Fa, Fb);
             }
             k = (k + 1u == a.spp) ? 0u : k + 1u;
             ++n;
@@ -403,9 +470,16 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
             }
         };
 
-        while (n < wend && (n & 15u) != 0u) one_step();
+        bool blocks = true;
+        if constexpr ((NOISE & NZ_JGRID) != 0) {
+            if (single) {
+                one_step(std::true_type{});
+                blocks = false;
+            }
+        }
+        while (blocks && n < wend && (n & 15u) != 0u) one_step(std::false_type{});
 
-        while (n + 16u <= wend) {
+        while (blocks && n + 16u <= wend) {
             U4 q[PPL];
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
@@ -457,10 +531,11 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
             for (int j = 0; j < PPL; ++j) fold<POT, R>(s[j]);   // x mod L at the block end
         }
 
-        while (n < wend) one_step();
+        while (n < wend) one_step(std::false_type{});
 
         // Countdowns at the window end: the next jump lies at or beyond it.  A window
-        // that ended early gives back the draws of the jumps queued past its end.
+        // that ended early gives back the draws of the jumps queued past its end
+        // (fixed grid); on the jump-adapted grid such kicks stay queued for the next.
         const bool early = wlen < wdrawn;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
@@ -470,15 +545,20 @@ __device__ __forceinline__ void advance_range(const PointConst &a, const uint32_
                     s[j].kP -= queued_beyond(kq + col(j), qs, wlen, wdrawn,
                                              [](const KickEntry<R> &e) { return e.off; });
             }
-            if constexpr ((NOISE & NZ_JGRID) != 0) {
-                s[j].sP = (int32_t)(J[j].poff - wlen);
-                s[j].thP = J[j].pth;
-            }
+            if constexpr ((NOISE & NZ_JGRID) != 0) jg_carry<R>(J[j], gq + col(j), qs, wlen);
             if constexpr ((NOISE & NZ_DICH) != 0) {
                 s[j].sD = (int32_t)(J[j].nD - wlen);
-                if ((NOISE & NZ_JGRID) == 0 && early)
+                if (early)
                     s[j].mD -= queued_beyond(fq + col(j), qs, wlen, wdrawn, [](uint32_t e) { return e; });
             }
+        }
+    }
+    if constexpr ((NOISE & NZ_JGRID) != 0) {
+        // every kick drawn lay before the last window's end and has been applied
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            s[j].sP = (int32_t)J[j].poff;
+            s[j].thP = J[j].pth;
         }
     }
 }
@@ -584,11 +664,15 @@ __global__ void __launch_bounds__(256) k_velocity(const KArgs a)
 
 // ---------------------------------------------------------------------------
 // Export of paths [n0, n0 + n1) (n0/n1 reused as first/count) to FP64 arrays and
-// to lossless per-path records (every field widened exactly).
+// to lossless per-path records (every field widened exactly).  flags (launch.hpp):
+// READ_VP the per-path velocity exists, READ_SNAP the window snapshot exists
+// (before the window start the record's window fields are 0, not the workspace's
+// unwritten contents).
 // ---------------------------------------------------------------------------
+
 template <typename R, int POT>
 __global__ void __launch_bounds__(256) k_read(const KArgs a, double *xo, double *vo, int64_t *no,
-                                              double *vpo, int with_vp, bm_path *so)
+                                              double *vpo, int flags, bm_path *so)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n1) return;
@@ -601,7 +685,7 @@ __global__ void __launch_bounds__(256) k_read(const KArgs a, double *xo, double 
     if (no) {
         for (int j = 0; j < 5; ++j) no[5 * i + j] = nz[j];
     }
-    if (vpo && with_vp) {
+    if (vpo && (flags & READ_VP)) {
         const double dx = (double)(a.w[p] - a.wi[p]) * L +
                           ((double)arr<R>(a.x)[p] - (double)arr<R>(a.xi)[p]);
         vpo[i] = dx / a.t_window;
@@ -611,8 +695,9 @@ __global__ void __launch_bounds__(256) k_read(const KArgs a, double *xo, double 
         r.periods = a.w[p];
         r.x = (double)arr<R>(a.x)[p];
         r.v = (double)arr<R>(a.v)[p];
-        r.periods_window = a.wi[p];
-        r.x_window = (double)arr<R>(a.xi)[p];
+        const bool snap = (flags & READ_SNAP) != 0;
+        r.periods_window = snap ? a.wi[p] : 0;
+        r.x_window = snap ? (double)arr<R>(a.xi)[p] : 0.0;
         r.kick_frac = a.thP ? a.thP[p] : 0.0;
         for (int j = 0; j < 5; ++j) r.noise[j] = nz[j];
         r.step_level = a.lev ? a.lev[p] : 0;

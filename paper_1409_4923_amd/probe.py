@@ -31,8 +31,8 @@ def lib() -> ctypes.CDLL:
 
 
 def valu_probe(mix: int, iters: int, d_out: int, n_out: int, stream: int) -> float:
-    """Lane-operations per second for mix 0 (FMA chains) or 1 (FMA + compare +
-    select); d_out: n_out device floats (a multiple of 256)."""
+    """Lane-operations per second for mix 0 (FMA chains), 1 (FMA + compare +
+    select) or 2 (FMA + exp2); d_out: n_out device floats (a multiple of 256)."""
     r = ctypes.c_double(0.0)
     rc = lib().bmp_valu_probe(mix, iters, d_out, n_out, stream, ctypes.byref(r))
     if rc != 0:

@@ -89,6 +89,20 @@ def train(sur: "B.Surrogate", x: np.ndarray, y: np.ndarray, epochs: int, batch: 
     return hist
 
 
+def uncertain_points(sur: "B.Surrogate", x: np.ndarray, n_pick: int, threshold: float) -> np.ndarray:
+    """Rows of candidate points x where the ensemble disagrees most: the n_pick largest
+    ensemble spreads among those above `threshold` (fewer if fewer exceed it), for the
+    next round of Monte Carlo labels (active learning)."""
+    import torch
+    xd = torch.tensor(np.asarray(x, dtype=np.float32), device=sur.device)
+    _, std, _, _ = sur.query(xd, threshold)
+    sd = std.cpu().numpy()
+    over = np.nonzero(~(sd <= threshold))[0]
+    if len(over) > n_pick:
+        over = over[np.argsort(-np.nan_to_num(sd[over], nan=np.inf), kind="stable")[:n_pick]]
+    return np.sort(over)
+
+
 @dataclass
 class QueryResult:
     value: np.ndarray          # surrogate mean, replaced by Monte Carlo where routed

@@ -21,11 +21,14 @@ def test_valu_probe_rates():
     peak = 256 * 64 * 2.4e9
     fma = PR.valu_probe(0, 2000, out.data_ptr(), n, stream)
     mixed = PR.valu_probe(1, 2000, out.data_ptr(), n, stream)
-    say("VALU probe: FMA %.3g, FMA+compare+select %.3g lane-ops/s (peak %.3g)" % (fma, mixed, peak))
+    trans = PR.valu_probe(2, 2000, out.data_ptr(), n, stream)
+    say("VALU probe: FMA %.3g, FMA+compare+select %.3g, FMA+exp2 %.3g lane-ops/s (peak %.3g)"
+        % (fma, mixed, trans, peak))
     assert 0.3 * peak < fma < 1.1 * peak
     assert mixed > 0.3 * peak
+    assert trans > 0.05 * peak
     assert torch.isfinite(out).all()
     with pytest.raises(PR.ProbeError):
         PR.valu_probe(0, 10, out.data_ptr(), 100, stream)
     with pytest.raises(PR.ProbeError):
-        PR.valu_probe(2, 10, out.data_ptr(), n, stream)
+        PR.valu_probe(3, 10, out.data_ptr(), n, stream)
