@@ -45,129 +45,131 @@ __global__ void __launch_bounds__(256) k_l1_fwd(const float *x, const uint32_t *
     a_out[row * H + o] = f2bf(gelu(z));
 }
 
-// Layer 4 (256 -> 1): one wave per row; grid (ceil(rows / 4), members).
-__global__ void __launch_bounds__(256) k_l4_fwd(const bf16_t *a3, const bf16_t *wbf, const float *params, int rows,
-                                                float *y)
-{
-    const int m = blockIdx.y, lane = threadIdx.x & 63;
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= rows) return;
-    const bf16_t *a = a3 + ((uint64_t)m * rows + r) * H;
-    const bf16_t *w = wbf + (uint64_t)m * NBF + BOFF_W4;
-    float s = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) s = fmaf(bf2f(a[lane * 4 + i]), bf2f(w[lane * 4 + i]), s);
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) y[(uint64_t)m * rows + r] = s + params[(uint64_t)m * NPARAM + OFF_B4];
-}
+// Output layer, loss and the output layer's gradients of the training step, fused.
+// Per row (one wave, four features per lane): y = a3 . W4 + b4, e = y - t,
+// dy = 2 e / B and dz3 = dy W4 gelu'(z3); per work-group of HEAD_ROWS rows the sums of
+// dy a3 (dW4), dy (db4) and e^2 (loss), combined over its waves in a fixed order.
+// grid (B / HEAD_ROWS, members), 256 lanes; B is a multiple of HEAD_ROWS.
+constexpr int HEAD_ROWS = 16;
+constexpr int HEAD_W = H + 2;          // partial record: dW4[256], db4, sum e^2
 
-// dy = 2 (y - t) / B and per-block sums of (y - t)^2; grid (ceil(B / 256), members).
-__global__ void __launch_bounds__(256) k_loss(const float *y, const float *t, const uint32_t *idx,
-                                              uint64_t idx_stride, int B, float *dy, float *partial)
+__global__ void __launch_bounds__(256) k_head(const bf16_t *a3, const float *z3, const bf16_t *wbf,
+                                              const float *params, const float *t, const uint32_t *idx,
+                                              uint64_t idx_stride, int B, bf16_t *dz3, float *hpart)
 {
-    __shared__ float red[256];
-    const int m = blockIdx.y, b = blockIdx.x * 256 + threadIdx.x;
-    float e2 = 0.0f;
-    if (b < B) {
-        const uint64_t src = idx ? (uint64_t)idx[(uint64_t)m * idx_stride + b] : (uint64_t)b;
-        const float e = y[(uint64_t)m * B + b] - t[src];
-        dy[(uint64_t)m * B + b] = 2.0f * e / (float)B;
-        e2 = e * e;
+    __shared__ float red[4][HEAD_W];
+    const int m = blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bf16_t *W4 = wbf + (uint64_t)m * NBF + BOFF_W4;
+    float w[4], sw[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[j] = bf2f(W4[lane * 4 + j]);
+    const float b4 = params[(uint64_t)m * NPARAM + OFF_B4];
+    float sb = 0.0f, se = 0.0f;
+#pragma unroll
+    for (int rr = 0; rr < HEAD_ROWS / 4; ++rr) {
+        const int r = blockIdx.x * HEAD_ROWS + wave * (HEAD_ROWS / 4) + rr;
+        const uint64_t row = (uint64_t)m * B + r;
+        float av[4];
+        float y = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            av[j] = bf2f(a3[row * H + lane * 4 + j]);
+            y = fmaf(av[j], w[j], y);
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) y += __shfl_xor(y, off, 64);   // the same sum in every lane
+        const uint64_t src = idx ? (uint64_t)idx[(uint64_t)m * idx_stride + r] : (uint64_t)r;
+        const float e = (y + b4) - t[src];
+        const float dy = 2.0f * e / (float)B;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            dz3[row * H + lane * 4 + j] = f2bf(dy * w[j] * gelu_grad(z3[row * H + lane * 4 + j]));
+            sw[j] = fmaf(dy, av[j], sw[j]);
+        }
+        sb += dy;
+        se = fmaf(e, e, se);
     }
-    red[threadIdx.x] = e2;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[wave][lane * 4 + j] = sw[j];
+    if (lane == 0) {
+        red[wave][H] = sb;
+        red[wave][H + 1] = se;
+    }
     __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[(uint64_t)m * gridDim.x + blockIdx.x] = red[0];
+    float *out = hpart + ((uint64_t)m * gridDim.x + blockIdx.x) * HEAD_W;
+    for (int o = threadIdx.x; o < HEAD_W; o += 256) out[o] = ((red[0][o] + red[1][o]) + red[2][o]) + red[3][o];
 }
 
-// loss[m] = sum of the block partials / B (fixed order).
-__global__ void k_loss_final(const float *partial, int nblk, int B, float *loss)
+// dW4, db4 and the loss of each member: the work-group partials added in order;
+// grid (members), 256 lanes.
+__global__ void __launch_bounds__(256) k_head_final(const float *hpart, int nblk, int B, float *grad, float *loss)
 {
-    const int m = threadIdx.x;
-    float s = 0.0f;
-    for (int i = 0; i < nblk; ++i) s += partial[(uint64_t)m * nblk + i];
-    loss[m] = s / (float)B;
+    const int m = blockIdx.x;
+    const float *p = hpart + (uint64_t)m * nblk * HEAD_W;
+    float *g = grad + (uint64_t)m * NPARAM;
+    for (int o = threadIdx.x; o < HEAD_W; o += 256) {
+        float s = 0.0f;
+#pragma unroll 8
+        for (int b = 0; b < nblk; ++b) s += p[(uint64_t)b * HEAD_W + o];
+        if (o < H) g[OFF_W4 + o] = s;
+        else if (o == H) g[OFF_B4] = s;
+        else if (loss) loss[m] = s / (float)B;
+    }
 }
 
-// Gradients that are column sums over the batch rather than GEMMs: the 1-wide
-// output layer (dW4 = sum_b dy[b] a3[b][:], db4 = sum_b dy[b]) and the 5-wide input
+// Gradients that are column sums over the batch rather than GEMMs: the 5-wide input
 // layer (dW1[o][j] = sum_b dz1[b][o] u[b][j], db1 = sum_b dz1[b][:]).  (The biases of
-// the 256 x 256 layers come with their weight-gradient GEMM.)  Pass 1: grid
+// the 256 x 256 layers come with their weight-gradient GEMM, the output layer with
+// k_head.)  Pass 1: grid
 // (n_chunks, members), lane = column o, each block sums one chunk of consecutive
 // rows; pass 2 adds the chunks in order, so the result does not depend on the launch.
-enum { RED_L4 = 1, RED_L1 = 2 };
-
-template <int KIND>
-struct RedWidth { static constexpr int value = KIND == RED_L4 ? 2 : IN + 1; };
-
 constexpr int RED_MAX_CHUNKS = 64;
+constexpr int NV1 = IN + 1;            // dW1[o][0..4], db1[o]
 
 __host__ __device__ inline int red_rows(int B) { return B / 64 < 16 ? 16 : B / 64; }
 
-template <int KIND>
-__global__ void __launch_bounds__(256) k_colsum(const bf16_t *dz, const float *dy, const bf16_t *a3,
-                                                const float *u, int B, int rows, float *part)
+__global__ void __launch_bounds__(256) k_colsum(const bf16_t *dz, const float *u, int B, int rows, float *part)
 {
-    constexpr int NV = RedWidth<KIND>::value;
     const int c = blockIdx.x, m = blockIdx.y, o = threadIdx.x, nchunk = gridDim.x;
-    float s[NV];
+    float s[NV1];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) s[q] = 0.0f;
+    for (int q = 0; q < NV1; ++q) s[q] = 0.0f;
     const uint64_t row0 = (uint64_t)m * B + (uint64_t)c * rows;
 #pragma unroll 8
     for (int r = 0; r < rows; ++r) {
         const uint64_t row = row0 + r;
-        if constexpr (KIND == RED_L4) {
-            const float d = dy[row];
-            s[0] = fmaf(d, bf2f(a3[row * H + o]), s[0]);
-            s[1] += d;
-        } else {
-            const float d = bf2f(dz[row * H + o]);
+        const float d = bf2f(dz[row * H + o]);
 #pragma unroll
-            for (int j = 0; j < IN; ++j) s[j] = fmaf(d, u[row * IN + j], s[j]);
-            s[IN] += d;
-        }
+        for (int j = 0; j < IN; ++j) s[j] = fmaf(d, u[row * IN + j], s[j]);
+        s[IN] += d;
     }
 #pragma unroll
-    for (int q = 0; q < NV; ++q) part[(((uint64_t)m * nchunk + c) * NV + q) * H + o] = s[q];
+    for (int q = 0; q < NV1; ++q) part[(((uint64_t)m * nchunk + c) * NV1 + q) * H + o] = s[q];
 }
 
-template <int KIND>
 __global__ void __launch_bounds__(256) k_colsum_final(const float *part, int nchunk, float *grad)
 {
-    constexpr int NV = RedWidth<KIND>::value;
     const int m = blockIdx.x, o = threadIdx.x;
-    float s[NV];
+    float s[NV1];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) s[q] = 0.0f;
+    for (int q = 0; q < NV1; ++q) s[q] = 0.0f;
     // the chunks in order; unrolled so that the loads of several chunks are in flight
 #pragma unroll 8
     for (int c = 0; c < nchunk; ++c) {
 #pragma unroll
-        for (int q = 0; q < NV; ++q) s[q] += part[(((uint64_t)m * nchunk + c) * NV + q) * H + o];
+        for (int q = 0; q < NV1; ++q) s[q] += part[(((uint64_t)m * nchunk + c) * NV1 + q) * H + o];
     }
     float *g = grad + (uint64_t)m * NPARAM;
-    if constexpr (KIND == RED_L4) {
-        g[OFF_W4 + o] = s[0];
-        if (o == 0) g[OFF_B4] = s[1];
-    } else {
 #pragma unroll
-        for (int j = 0; j < IN; ++j) g[OFF_W1 + o * IN + j] = s[j];
-        g[OFF_B1 + o] = s[IN];
-    }
+    for (int j = 0; j < IN; ++j) g[OFF_W1 + o * IN + j] = s[j];
+    g[OFF_B1 + o] = s[IN];
 }
 
-template <int KIND>
-hipError_t colsum(uint32_t nm, int B, const bf16_t *dz, const float *dy, const bf16_t *a3, const float *u,
-                  float *part, float *grad, hipStream_t s)
+hipError_t colsum(uint32_t nm, int B, const bf16_t *dz, const float *u, float *part, float *grad, hipStream_t s)
 {
     const int rows = red_rows(B), nchunk = B / rows;
-    hipLaunchKernelGGL(k_colsum<KIND>, dim3(nchunk, nm), dim3(256), 0, s, dz, dy, a3, u, B, rows, part);
-    hipLaunchKernelGGL(k_colsum_final<KIND>, dim3(nm), dim3(256), 0, s, (const float *)part, nchunk, grad);
+    hipLaunchKernelGGL(k_colsum, dim3(nchunk, nm), dim3(256), 0, s, dz, u, B, rows, part);
+    hipLaunchKernelGGL(k_colsum_final, dim3(nm), dim3(256), 0, s, (const float *)part, nchunk, grad);
     return hipGetLastError();
 }
 
@@ -189,16 +191,6 @@ __global__ void __launch_bounds__(256) k_wgrad_sum(const float *wpart, const flo
         for (int kc = 0; kc < ks; ++kc) s += bpart[((uint64_t)kc * nm + m) * H + t];
         g[boff + t] = s;
     }
-}
-
-// dz3 = dy W4 gelu'(z3), grid (B, members), lane = column.
-__global__ void __launch_bounds__(256) k_l4_bwd_dz(const float *dy, const bf16_t *wbf, const float *z3, int B,
-                                                   bf16_t *dz3)
-{
-    const int b = blockIdx.x, m = blockIdx.y, i = threadIdx.x;
-    const uint64_t row = (uint64_t)m * B + b;
-    const float w = bf2f(wbf[(uint64_t)m * NBF + BOFF_W4 + i]);
-    dz3[row * H + i] = f2bf(dy[row] * w * gelu_grad(z3[row * H + i]));
 }
 
 // BF16 index of parameter p of a member, or -1 for biases.
@@ -323,7 +315,7 @@ __global__ void __launch_bounds__(256) k_compact(const float *stdv, uint64_t B, 
 size_t up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct MlpLayout {
-    size_t u, z1, z2, z3, a1, a2, a3, y, dy, dz1, dz2, dz3, part, red, wpart, bpart, mean, stdv, blk, total;
+    size_t u, z1, z2, z3, a1, a2, a3, y, dz1, dz2, dz3, hpart, red, wpart, bpart, blk, total;
 };
 
 // Split of the batch (the K of the weight-gradient GEMMs) over work-groups: the
@@ -346,22 +338,19 @@ MlpLayout mlp_layout(uint32_t nm, uint64_t batch, bool training)
         L.a1 = take(nm * R * H * 2);
         L.a2 = take(nm * R * H * 2);
         L.a3 = take(nm * R * H * 2);
-    }
-    L.y = take(nm * batch * 4);
-    if (training) {
         L.u = take(nm * R * IN * 4);
         L.z1 = take(nm * R * H * 4);
         L.z2 = take(nm * R * H * 4);
         L.z3 = take(nm * R * H * 4);
-        L.dy = take(nm * R * 4);
         L.dz1 = take(nm * R * H * 2);
         L.dz2 = take(nm * R * H * 2);
         L.dz3 = take(nm * R * H * 2);
-        L.part = take(nm * ((R + 255) / 256) * 4);
-        L.red = take((size_t)nm * RED_MAX_CHUNKS * (IN + 1) * H * 4);
+        L.hpart = take(nm * (R / HEAD_ROWS) * HEAD_W * 4);
+        L.red = take((size_t)nm * RED_MAX_CHUNKS * NV1 * H * 4);
         L.wpart = take((size_t)WG_MAX_SPLIT * nm * H * H * 4);
         L.bpart = take((size_t)WG_MAX_SPLIT * nm * H * 4);
     } else {
+        L.y = take(nm * batch * 4);
         L.blk = take(((batch + 255) / 256) * 4 + 4);
     }
     L.total = o;
@@ -559,10 +548,11 @@ __global__ void __launch_bounds__(64 * 8 / RT) k_mlp_infer(const float *x, uint6
     }
 }
 
-// Training forward of `rows` rows through all members, keeping what backward needs
-// (normalised inputs, pre-activations z, BF16 activations); y[m * rows + r].
+// Training forward of `rows` rows through layers 1-3 of all members, keeping what
+// backward needs (normalised inputs, pre-activations z, BF16 activations); the output
+// layer runs fused with the loss (k_head).
 hipError_t train_forward(uint32_t nm, const float *params, const bf16_t *wbf, const float *x, const uint32_t *idx,
-                         uint64_t idx_stride, int rows, char *ws, const MlpLayout &L, float *y, hipStream_t s)
+                         uint64_t idx_stride, int rows, char *ws, const MlpLayout &L, hipStream_t s)
 {
     bf16_t *a1 = (bf16_t *)(ws + L.a1), *a2 = (bf16_t *)(ws + L.a2), *a3 = (bf16_t *)(ws + L.a3);
     float *u = (float *)(ws + L.u), *z1 = (float *)(ws + L.z1);
@@ -586,8 +576,7 @@ hipError_t train_forward(uint32_t nm, const float *params, const bf16_t *wbf, co
         e = gemm<EPI_FWD, false, false>(g, (int)nm, s);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_l4_fwd, dim3((uint32_t)((rows + 3) / 4), nm), dim3(256), 0, s, a3, wbf, params, rows, y);
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 } // namespace
@@ -677,28 +666,21 @@ extern "C" int bm_mlp_backward(uint32_t n_members, const float *d_params, const 
     const int B = (int)batch;
     const uint32_t nm = n_members;
     const bf16_t *wbf = (const bf16_t *)d_wbf;
-    float *y = (float *)(ws + L.y), *dy = (float *)(ws + L.dy), *u = (float *)(ws + L.u);
+    float *u = (float *)(ws + L.u);
     float *z1 = (float *)(ws + L.z1), *z2 = (float *)(ws + L.z2), *z3 = (float *)(ws + L.z3);
     bf16_t *a1 = (bf16_t *)(ws + L.a1), *a2 = (bf16_t *)(ws + L.a2), *a3 = (bf16_t *)(ws + L.a3);
     bf16_t *dz1 = (bf16_t *)(ws + L.dz1), *dz2 = (bf16_t *)(ws + L.dz2), *dz3 = (bf16_t *)(ws + L.dz3);
-    float *part = (float *)(ws + L.part), *red = (float *)(ws + L.red);
+    float *hpart = (float *)(ws + L.hpart), *red = (float *)(ws + L.red);
 
-    hipError_t e = train_forward(nm, d_params, wbf, d_x, d_idx, batch, B, ws, L, y, s);
-    const int nblk = (B + 255) / 256;
+    hipError_t e = train_forward(nm, d_params, wbf, d_x, d_idx, batch, B, ws, L, s);
+    // output layer, loss, dW4 / db4 and dz3
+    const int nhead = B / HEAD_ROWS;
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_loss, dim3(nblk, nm), dim3(256), 0, s, y, d_t, d_idx, batch, B, dy, part);
+        hipLaunchKernelGGL(k_head, dim3(nhead, nm), dim3(256), 0, s, (const bf16_t *)a3, (const float *)z3, wbf,
+                           d_params, d_t, d_idx, batch, B, dz3, hpart);
+        hipLaunchKernelGGL(k_head_final, dim3(nm), dim3(256), 0, s, (const float *)hpart, nhead, B, d_grad,
+                           d_loss);
         e = hipGetLastError();
-    }
-    if (e == hipSuccess && d_loss) {
-        hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(nm), 0, s, part, nblk, B, d_loss);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) {
-        e = colsum<RED_L4>(nm, B, nullptr, dy, a3, nullptr, red, d_grad, s);
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_l4_bwd_dz, dim3(B, nm), dim3(256), 0, s, dy, wbf, z3, B, dz3);
-            e = hipGetLastError();
-        }
     }
     // layers 3 and 2: weight gradients dW = dz^T a_prev, bias gradients, and dz_prev
     const bf16_t *dzs[2] = {dz3, dz2};
@@ -733,7 +715,7 @@ extern "C" int bm_mlp_backward(uint32_t n_members, const float *d_params, const 
         e = gemm<EPI_DGRAD, false, true>(d, (int)nm, s);
     }
     if (e == hipSuccess) {
-        e = colsum<RED_L1>(nm, B, dz1, nullptr, nullptr, u, red, d_grad, s);
+        e = colsum(nm, B, dz1, u, red, d_grad, s);
     }
     return e == hipSuccess ? ok() : hip_fail(e, "bm_mlp_backward");
 }
@@ -817,3 +799,5 @@ extern "C" int bm_surrogate_query(uint32_t n_members, const float *d_params, con
                                        (uint32_t *)(ws + L.blk), (hipStream_t)stream);
     return e == hipSuccess ? ok() : hip_fail(e, "bm_surrogate_query");
 }
+
+

@@ -234,51 +234,86 @@ __device__ __forceinline__ void jg_advance(const PointConst &a, uint32_t path, u
 // (one per further kick in the step, then the rest of the step).  The first piece
 // takes the step's own Gaussian increment scaled by sqrt(theta); a piece after
 // kick k takes the increment drawn for k.
+// The pieces of a kicked lane's step after its first kick (at fraction `from`, drive
+// A_from there, u the increment of the next piece): one per further kick in the step,
+// then the rest of the step.  The cursor already points past the first kick.
+template <typename R, int DYN, int POT, int NOISE, bool INL>
+__device__ __forceinline__ void jg_rest(const PointConst &a, uint32_t path, Path<R> &s, JumpCursor<R> &J,
+                                        const JGKick<R> *q, uint32_t qs, uint32_t wlen, uint32_t off,
+                                        uint32_t kph, R h, R hh, R ngam, R kp, R A1, R lev, R from, R A_from, R u)
+{
+    // further kicks in this step (lambda dt <= 16 is enforced on the host; the bound
+    // only guarantees that every lane leaves the loop)
+    for (uint32_t it = 0; J.g.off == off && it < JG_MAX_KICKS; ++it) {
+        const R th = J.g.th;
+        const R A_th = drive_inside<R>(a, kph, (double)th) + lev;
+        pc_step<DYN, POT, true, R>(s, (th - from) * h, (th - from) * hh, ngam, kp, u * piece_sqrt(th - from), J.g.z,
+                                   A_from, A_th);
+        from = th;
+        A_from = A_th;
+        u = J.g.u;
+        jg_advance<R, NOISE, INL>(a, path, wlen, s.kP, J, q, qs);
+    }
+    pc_step<DYN, POT, false, R>(s, (R(1) - from) * h, (R(1) - from) * hh, ngam, kp, u * piece_sqrt(R(1) - from), R(0),
+                                A_from, A1);
+}
+
 template <typename R, int DYN, int POT, int NOISE, bool INL>
 __device__ __forceinline__ void jg_step(const PointConst &a, uint32_t path, Path<R> &s, JumpCursor<R> &J,
                                         const JGKick<R> *q, uint32_t qs, uint32_t wlen, uint32_t off,
                                         uint32_t kph, R dxi, R h, R hh, R ngam, R kp, R A0, R A1, R lev)
 {
     const bool kick = J.g.off == off;
-    if (__builtin_amdgcn_ballot_w64(kick) == 0) {           // no lane of the wave kicks now
-        pc_step<DYN, POT, false, R>(s, h, hh, ngam, kp, dxi, R(0), A0, A1);
-        return;
-    }
+    const bool any = __builtin_amdgcn_ballot_w64(kick) != 0;      // some lane of the wave kicks now
     R th1 = R(1), A_e = A1, dxi1 = dxi, z1 = R(0);
-    if constexpr (sizeof(R) == 4) {
-        // FP32: the kick's values formed in every lane and selected (no divergent
-        // branch; the cosine and square root go to the transcendental unit)
-        const R thk = J.g.th;
-        const R A_k = drive_inside<R>(a, kph, (double)thk) + lev;
-        const R dxk = dxi * piece_sqrt(thk);
-        th1 = kick ? thk : R(1);
-        A_e = kick ? A_k : A1;
-        dxi1 = kick ? dxk : dxi;
-        z1 = kick ? J.g.z : R(0);
-    } else if (kick) {
-        th1 = J.g.th;
-        A_e = drive_inside<R>(a, kph, (double)th1) + lev;
-        dxi1 = dxi * piece_sqrt(th1);
-        z1 = J.g.z;
-    }
-    pc_step<DYN, POT, true, R>(s, th1 * h, th1 * hh, ngam, kp, dxi1, z1, A0, A_e);
-    if (kick) {
-        R from = th1, A_from = A_e, u = J.g.u;
-        jg_advance<R, NOISE, INL>(a, path, wlen, s.kP, J, q, qs);
-        // further kicks in this step (lambda dt <= 16 is enforced on the host; the
-        // bound only guarantees that every lane leaves the loop)
-        for (uint32_t it = 0; J.g.off == off && it < JG_MAX_KICKS; ++it) {
-            const R th = J.g.th;
-            const R A_th = drive_inside<R>(a, kph, (double)th) + lev;
-            pc_step<DYN, POT, true, R>(s, (th - from) * h, (th - from) * hh, ngam, kp, u * piece_sqrt(th - from), J.g.z,
-                                       A_from, A_th);
-            from = th;
-            A_from = A_th;
-            u = J.g.u;
-            jg_advance<R, NOISE, INL>(a, path, wlen, s.kP, J, q, qs);
+    if constexpr (sizeof(R) == 4 && !INL) {
+        // FP32: one instance of the first piece for every step.  When a lane of the
+        // wave kicks, the kick's length, drive, increment and amplitude are formed in
+        // every lane and selected (no divergent branch; the cosine and the square root
+        // go to the transcendental unit); otherwise the piece is the whole step
+        // (th1 = 1 makes th1 dt exact).
+        if (any) {
+            const R thk = J.g.th;
+            const R A_k = drive_inside<R>(a, kph, (double)thk) + lev;
+            const R dxk = dxi * piece_sqrt(thk);
+            th1 = kick ? thk : R(1);
+            A_e = kick ? A_k : A1;
+            dxi1 = kick ? dxk : dxi;
+            z1 = kick ? J.g.z : R(0);
         }
-        pc_step<DYN, POT, false, R>(s, (R(1) - from) * h, (R(1) - from) * hh, ngam, kp, u * piece_sqrt(R(1) - from),
-                                    R(0), A_from, A1);
+        pc_step<DYN, POT, true, R>(s, th1 * h, th1 * hh, ngam, kp, dxi1, z1, A0, A_e);
+        if (!any) return;
+        // the kicked lanes' cursors move on: every lane reads the entry after its
+        // cursor, the kicked lanes take it
+        const R u_after = J.g.u;                 // increment of the piece after the kick
+        const uint32_t nidx = J.gs < J.gn ? J.gs + 1u : J.gs;
+        const bool more = nidx < J.gn;
+        const JGKick<R> e = q[(more ? nidx : 0u) * qs];
+        J.gs = kick ? nidx : J.gs;
+        J.g.off = kick ? (more ? e.off : JG_NONE) : J.g.off;
+        J.g.th = kick ? e.th : J.g.th;
+        J.g.z = kick ? e.z : J.g.z;
+        J.g.u = kick ? e.u : J.g.u;
+        if (kick) jg_rest<R, DYN, POT, NOISE, INL>(a, path, s, J, q, qs, wlen, off, kph, h, hh, ngam, kp, A1, lev,
+                                                   th1, A_e, u_after);
+    } else {
+        if (!any) {
+            pc_step<DYN, POT, false, R>(s, h, hh, ngam, kp, dxi, R(0), A0, A1);
+            return;
+        }
+        if (kick) {
+            th1 = J.g.th;
+            A_e = drive_inside<R>(a, kph, (double)th1) + lev;
+            dxi1 = dxi * piece_sqrt(th1);
+            z1 = J.g.z;
+        }
+        pc_step<DYN, POT, true, R>(s, th1 * h, th1 * hh, ngam, kp, dxi1, z1, A0, A_e);
+        if (kick) {
+            const R u_after = J.g.u;
+            jg_advance<R, NOISE, INL>(a, path, wlen, s.kP, J, q, qs);
+            jg_rest<R, DYN, POT, NOISE, INL>(a, path, s, J, q, qs, wlen, off, kph, h, hh, ngam, kp, A1, lev, th1,
+                                             A_e, u_after);
+        }
     }
 }
 

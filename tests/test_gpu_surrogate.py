@@ -67,3 +67,46 @@ def test_surrogate_gain_over_monte_carlo():
     say("MC %.1f points/s, surrogate %.1f points/s (fallback %.3f), gain %.1f"
         % (1 / mc_cost, sur_rate, f, sur_rate * mc_cost))
     assert sur_rate * mc_cost > 10.0
+
+
+def test_surrogate_on_the_configured_domain_is_tracked():
+    """The whole configured domain (multistable regions included), with a small label
+    budget and one round of labels where the ensemble disagrees most: the answered
+    held-out points stay within 0.01 of the Monte Carlo truth (p95), the ensemble
+    answers a fair share of the queries itself, and the fallback fraction and gain over
+    plain MC are reported (the benchmark tracks them at full size)."""
+    import torch
+    tol, thr = 0.01, 0.005
+    xl = W.surrogate_queries(60000, seed=21)
+    lab = S.monte_carlo(xl, 256, 100, seed=1)
+    sur = B.Surrogate(5, seed=3)
+    S.train(sur, xl, lab.mean, epochs=60, batch=1024, lr=2e-3, seed=4)
+    xc = W.surrogate_queries(300_000, seed=22)
+    pick = S.uncertain_points(sur, xc, 30000, thr)
+    assert 0 < len(pick) <= 30000
+    _, sd, _, _ = sur.query(torch.tensor(xc, device="cuda"), thr)
+    sd = sd.cpu().numpy()
+    # the picked points are the largest spreads above the threshold
+    rest = np.setdiff1d(np.nonzero(sd > thr)[0], pick)
+    assert np.all(sd[pick] > thr)
+    assert len(rest) == 0 or np.min(sd[pick]) >= np.max(sd[rest])
+    lab_a = S.monte_carlo(xc[pick], 256, 100, seed=1, first_point=1 << 22)
+    xa, ya = np.concatenate([xl, xc[pick]]), np.concatenate([lab.mean, lab_a.mean])
+    S.train(sur, xa, ya, epochs=40, batch=1024, lr=1e-3, seed=5)
+    xh = W.surrogate_queries(1000, seed=23)
+    truth = S.monte_carlo(xh, 4096, 100, seed=2, first_point=1 << 24)
+    mean, std, _, _ = sur.query(torch.tensor(xh, device="cuda"), thr)
+    mean, std = mean.cpu().numpy(), std.cpu().numpy()
+    keep = std <= thr
+    err = np.abs(mean - truth.mean)
+    rate = truth.path_steps / truth.seconds
+    need = np.maximum(64.0, np.ceil((3.0 * np.nan_to_num(truth.std, nan=1.0) / tol) ** 2))
+    cost = need * 100 * S.SPP / rate
+    f = 1.0 - keep.mean()
+    gain = float(np.mean(cost)) / (f * float(np.mean(cost[~keep])) if f > 0 else 1e-9)
+    say("full domain: %d + %d labels, answered %.3f of held-out, p95 |err| %.4f, fallback %.3f, "
+        "routed points cost %.2fx the mean, gain %.2f"
+        % (len(xl), len(pick), keep.mean(), np.percentile(err[keep], 95) if keep.any() else -1, f,
+           float(np.mean(cost[~keep])) / float(np.mean(cost)) if f > 0 else 0.0, gain))
+    assert keep.mean() > 0.3
+    assert np.percentile(err[keep], 95) <= tol
