@@ -408,6 +408,22 @@ int bm_surrogate_query(uint32_t n_members, const float *d_params, const uint16_t
                        uint64_t batch, float threshold, float *d_mean, float *d_std, uint32_t *d_fallback_idx,
                        uint32_t *d_fallback_count, void *d_ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): bm_surrogate_query with the
+ * same arguments, results and kernels, but no workspace.  The members' predictions
+ * and the routing counts go to a scratch array of BM_QUERY_SCRATCH_BYTES built into
+ * the library, one per GPU, held from the first call on that GPU until the process
+ * ends; the call itself allocates nothing.  A query needs
+ * bm_mlp_workspace_size(n_members, batch, 0) bytes of it (5 members x 10^6 rows fit);
+ * larger queries get BM_ERR_WORKSPACE and must use bm_surrogate_query.  Every call
+ * on one GPU uses that GPU's one array: calls that overlap on one GPU (on different
+ * streams, or from different threads without ordering) race and give undefined
+ * results; calls ordered on one stream are safe. */
+#define BM_QUERY_SCRATCH_BYTES 33554432u
+int bm_surrogate_query_noalloc(uint32_t n_members, const float *d_params, const uint16_t *d_wbf,
+                               const float *d_x, uint64_t batch, float threshold, float *d_mean, float *d_std,
+                               uint32_t *d_fallback_idx, uint32_t *d_fallback_count, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

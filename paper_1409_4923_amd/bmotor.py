@@ -122,9 +122,12 @@ SIGNATURES = [
                                    ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp]),
     ("bm_surrogate_query", ctypes.c_int, [ctypes.c_uint32, _vp, _vp, _vp, ctypes.c_uint64, ctypes.c_float, _vp,
                                           _vp, _vp, _vp, _vp, _sz, _vp]),
+    ("bm_surrogate_query_noalloc", ctypes.c_int, [ctypes.c_uint32, _vp, _vp, _vp, ctypes.c_uint64, ctypes.c_float,
+                                                  _vp, _vp, _vp, _vp, _vp]),
 ]
 
 BM_MLP_INPUTS, BM_MLP_HIDDEN, BM_MLP_PARAMS, BM_MLP_BF16, BM_MLP_MAX_MEMBERS = 5, 256, 133377, 132608, 16
+BM_QUERY_SCRATCH_BYTES = 33554432
 
 
 def lib() -> ctypes.CDLL:
@@ -563,6 +566,12 @@ def bm_surrogate_query(n_members, d_params, d_wbf, d_x, batch, threshold, d_mean
                        ws_bytes, stream) -> None:
     check(lib().bm_surrogate_query(n_members, d_params, d_wbf, d_x, batch, threshold, d_mean, d_std, d_fidx,
                                    d_fcount, d_ws, ws_bytes, stream))
+
+
+def bm_surrogate_query_noalloc(n_members, d_params, d_wbf, d_x, batch, threshold, d_mean, d_std, d_fidx, d_fcount,
+                               stream) -> None:
+    check(lib().bm_surrogate_query_noalloc(n_members, d_params, d_wbf, d_x, batch, threshold, d_mean, d_std, d_fidx,
+                                           d_fcount, stream))
 
 
 class Surrogate:

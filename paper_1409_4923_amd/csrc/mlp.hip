@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "bmotor.h"
 #include "common.hpp"
@@ -801,3 +802,64 @@ extern "C" int bm_surrogate_query(uint32_t n_members, const float *d_params, con
 }
 
 
+// ---------------------------------------------------------------------------
+// Ensemble query without a caller workspace and without any allocation: the
+// members' predictions and the per-256-row counts live in `scratch`, a file-scope
+// device array (one copy per GPU, held until the process ends).  In host code the
+// array's name stands for a host-side shadow, so its device address is looked up
+// once per device with hipGetSymbolAddress and only that address is ever passed to
+// a kernel.  Every element a query reads is first written by the same query, so
+// the array needs no clearing between calls.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[BM_QUERY_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_dev[SCRATCH_MAX_DEVICES];     // device address of `scratch` on each device
+
+// Device address of `scratch` on device `dev` (the current device), looked up on the
+// first call for that device.
+int scratch_address(int dev, char **out)
+{
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+        return fail(BM_ERR_DEVICE, "device index %d beyond the %d the scratch table holds", dev,
+                    SCRATCH_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(BM_ERR_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        scratch_dev[dev] = p;
+    }
+    *out = (char *)scratch_dev[dev];
+    return BM_OK;
+}
+} // namespace
+
+extern "C" int bm_surrogate_query_noalloc(uint32_t n_members, const float *d_params, const uint16_t *d_wbf,
+                                          const float *d_x, uint64_t batch, float threshold, float *d_mean,
+                                          float *d_std, uint32_t *d_fallback_idx, uint32_t *d_fallback_count,
+                                          void *stream)
+{
+    int rc = check_query(n_members, d_params, d_wbf, d_x, batch, threshold, d_mean, d_std, d_fallback_idx,
+                         d_fallback_count);
+    if (rc) return rc;
+    const MlpLayout L = mlp_layout(n_members, batch, false);
+    if (L.total > BM_QUERY_SCRATCH_BYTES)
+        return fail(BM_ERR_WORKSPACE,
+                    "query of %u members x %llu rows needs %zu B of scratch; the built-in scratch holds %zu B "
+                    "(use bm_surrogate_query with a workspace)",
+                    n_members, (unsigned long long)batch, L.total, (size_t)BM_QUERY_SCRATCH_BYTES);
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    char *ws = nullptr;
+    rc = scratch_address(dev, &ws);
+    if (rc) return rc;
+    const hipError_t e = enqueue_query(n_members, d_params, d_wbf, d_x, batch, threshold, d_mean, d_std,
+                                       d_fallback_idx, d_fallback_count, (float *)(ws + L.y),
+                                       (uint32_t *)(ws + L.blk), (hipStream_t)stream);
+    return e == hipSuccess ? ok() : hip_fail(e, "bm_surrogate_query_noalloc");
+}
