@@ -456,7 +456,7 @@ def surrogate_leg(args):
     print("surrogate: %d labels in %.1f s" % (args.labels, lab.seconds), file=sys.stderr, flush=True)
     sur = B.Surrogate(5, seed=7)
     t0 = time.perf_counter()
-    hist = S.train(sur, xl, yl, epochs=args.epochs, batch=1024, lr=2e-3, seed=3)
+    hist = S.train(sur, xl, yl, epochs=args.epochs, batch=args.batch, lr=args.lr, seed=3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     print("surrogate: trained in %.1f s, loss %.4g -> %.4g" % (t_train, hist[0], hist[-1]), file=sys.stderr,
@@ -475,7 +475,7 @@ def surrogate_leg(args):
         xl = np.concatenate([xl, xc[pick]])
         yl = np.concatenate([yl, lab_a.mean])
         t0 = time.perf_counter()
-        h = S.train(sur, xl, yl, epochs=args.active_epochs, batch=1024, lr=1e-3, seed=4 + rd)
+        h = S.train(sur, xl, yl, epochs=args.active_epochs, batch=args.batch, lr=args.lr / 2, seed=4 + rd)
         torch.cuda.synchronize()
         t_tr = time.perf_counter() - t0
         t_label += lab_a.seconds + t_pick
@@ -523,7 +523,7 @@ def surrogate_leg(args):
     flops = n_q * 5 * 2 * (5 * 256 + 2 * 256 * 256 + 256)
     return {"labels": int(len(xl)), "labels_uniform": args.labels, "active_rounds": rounds,
             "label_budget": [args.label_paths, args.label_periods],
-            "label_seconds": t_label, "train_seconds": t_train, "epochs": args.epochs,
+            "label_seconds": t_label, "train_seconds": t_train, "epochs": args.epochs, "batch": args.batch,
             "train_loss": [hist[0], hist[-1]],
             "heldout": args.heldout, "truth_paths": args.truth_paths, "truth_se_median": float(np.median(truth.se)),
             "queries": n_q, "threshold": thr, "query_seconds": t_query,
@@ -555,13 +555,17 @@ def main():
     ap.add_argument("--legs", default="c3,c2jump,scan,scheme,infer,surrogate",
                     help="extra legs: c3, c2jump, scan, scheme, infer, surrogate (or none)")
     ap.add_argument("--labels", type=int, default=100_000, help="uniform labels before active learning")
-    ap.add_argument("--active-rounds", type=int, default=1)
+    ap.add_argument("--active-rounds", type=int, default=0,
+                    help="rounds of labels where the ensemble disagrees most (measured to raise the fallback "
+                         "fraction on this domain, so off by default)")
     ap.add_argument("--active-labels", type=int, default=100_000, help="labels added per active round")
     ap.add_argument("--active-candidates", type=int, default=1_000_000)
     ap.add_argument("--active-epochs", type=int, default=100)
     ap.add_argument("--label-paths", type=int, default=256)
     ap.add_argument("--label-periods", type=int, default=100)
-    ap.add_argument("--epochs", type=int, default=150)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--batch", type=int, default=1024, help="surrogate training minibatch")
+    ap.add_argument("--lr", type=float, default=2e-3, help="surrogate training learning rate (start)")
     ap.add_argument("--heldout", type=int, default=10_000)
     ap.add_argument("--truth-paths", type=int, default=4096)
     ap.add_argument("--queries", type=int, default=1_000_000)

@@ -148,29 +148,24 @@ __global__ void __launch_bounds__(256) k_colsum(const bf16_t *dz, const float *u
     for (int q = 0; q < NV1; ++q) part[(((uint64_t)m * nchunk + c) * NV1 + q) * H + o] = s[q];
 }
 
+// grid (NV1, members): block q adds the chunks of sum q (dW1[:][q], or db1 for q = IN).
 __global__ void __launch_bounds__(256) k_colsum_final(const float *part, int nchunk, float *grad)
 {
-    const int m = blockIdx.x, o = threadIdx.x;
-    float s[NV1];
-#pragma unroll
-    for (int q = 0; q < NV1; ++q) s[q] = 0.0f;
+    const int q = blockIdx.x, m = blockIdx.y, o = threadIdx.x;
+    float s = 0.0f;
     // the chunks in order; unrolled so that the loads of several chunks are in flight
 #pragma unroll 8
-    for (int c = 0; c < nchunk; ++c) {
-#pragma unroll
-        for (int q = 0; q < NV1; ++q) s[q] += part[(((uint64_t)m * nchunk + c) * NV1 + q) * H + o];
-    }
+    for (int c = 0; c < nchunk; ++c) s += part[(((uint64_t)m * nchunk + c) * NV1 + q) * H + o];
     float *g = grad + (uint64_t)m * NPARAM;
-#pragma unroll
-    for (int j = 0; j < IN; ++j) g[OFF_W1 + o * IN + j] = s[j];
-    g[OFF_B1 + o] = s[IN];
+    if (q < IN) g[OFF_W1 + o * IN + q] = s;
+    else g[OFF_B1 + o] = s;
 }
 
 hipError_t colsum(uint32_t nm, int B, const bf16_t *dz, const float *u, float *part, float *grad, hipStream_t s)
 {
     const int rows = red_rows(B), nchunk = B / rows;
     hipLaunchKernelGGL(k_colsum, dim3(nchunk, nm), dim3(256), 0, s, dz, u, B, rows, part);
-    hipLaunchKernelGGL(k_colsum_final, dim3(nm), dim3(256), 0, s, (const float *)part, nchunk, grad);
+    hipLaunchKernelGGL(k_colsum_final, dim3(NV1, nm), dim3(256), 0, s, (const float *)part, nchunk, grad);
     return hipGetLastError();
 }
 

@@ -274,7 +274,8 @@ __device__ __forceinline__ void jg_step(const PointConst &a, uint32_t path, Path
         // (th1 = 1 makes th1 dt exact).
         if (any) {
             const R thk = J.g.th;
-            const R A_k = drive_inside<R>(a, kph, (double)thk) + lev;
+            R A_k = drive_inside<R>(a, kph, (double)thk);
+            if constexpr ((NOISE & NZ_DICH) != 0) A_k = A_k + lev;
             const R dxk = dxi * piece_sqrt(thk);
             th1 = kick ? thk : R(1);
             A_e = kick ? A_k : A1;
