@@ -40,10 +40,10 @@ FP64_PEAK_FLOPS = 78.6e12
 # reads 0.5 GiB for it: factor 2.0; WRITE_SIZE reads 1 GiB: factor 1.0).  Valid
 # only while the integration kernel's sources hash to KERNEL_SOURCES_SHA256.
 TRAFFIC_WORKLOAD = "inertial-poisson-f32-2^20"
-TRAFFIC_BYTES_PER_LAUNCH = ((10524.0625 + 10327.0) / 2 * 2.0 + (28672.0 + 20480.0) / 2 * 1.0) * 1024
+TRAFFIC_BYTES_PER_LAUNCH = ((10528.0625 + 10335.0) / 2 * 2.0 + (28672.0 + 20480.0) / 2 * 1.0) * 1024
 KERNEL_SOURCES = ("common.hpp", "paths.hpp", "paths_kernels.hpp", "paths_tu.inc", "paths_f32_in.hip",
                   "launch.hpp")
-KERNEL_SOURCES_SHA256 = "e5b7cb09b6cad74670e1eaecdcaa9c1e43f3903a34a9114e6d6a8845682ab00f"
+KERNEL_SOURCES_SHA256 = "d6fbeecabe7d6e2b68fcf7361058bc72e5508394e0aa8650ead8592aa18b704f"
 
 
 def algorithmic_work(w):
@@ -554,7 +554,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="c3,c2jump,scan,scheme,infer,surrogate",
                     help="extra legs: c3, c2jump, scan, scheme, infer, surrogate (or none)")
-    ap.add_argument("--labels", type=int, default=100_000, help="uniform labels before active learning")
+    ap.add_argument("--labels", type=int, default=60_000, help="uniform labels before active learning")
     ap.add_argument("--active-rounds", type=int, default=0,
                     help="rounds of labels where the ensemble disagrees most (measured to raise the fallback "
                          "fraction on this domain, so off by default)")
