@@ -392,17 +392,23 @@ GemmArgs gemm_args()
 // ---------------------------------------------------------------------------
 // Fused inference: one work-group runs 128 rows of one member through all four
 // layers; activations never leave the registers.  The 256 x 256 layers are
-// computed transposed, Z^T = W A^T, with W as the MFMA A operand (staged through
-// LDS one 16-row tile at a time, triple-buffered) and the activations as the B
-// operand: a 16 x 16 output tile leaves lane (g = lane/16, c = lane%16) holding
-// features 4g..4g+3 of row c, which is exactly the B-operand slot of the next
-// layer if its contraction index is permuted -- k-step s, slot j of lane group g
-// stands for feature 32 s + 4 g + j (j < 4) or 32 s + 16 + 4 g + (j - 4) (j >= 4),
-// and the W fragments are read from LDS in that order.
+// computed transposed, Z^T = W A^T, with W as the MFMA A operand and the
+// activations as the B operand: a 16 x 16 output tile leaves lane (g = lane/16,
+// c = lane%16) holding features 4g..4g+3 of row c, which is exactly the B-operand
+// slot of the next layer if its contraction index is permuted -- k-step s, slot j
+// of lane group g stands for feature 32 s + 4 g + j (j < 4) or 32 s + 16 + 4 g +
+// (j - 4) (j >= 4), and the W fragments are read from LDS in that order.
+// The contraction runs outermost: each wave keeps the accumulators of all 16 output
+// tiles of its 32 rows (128 registers) and walks the 8 k-steps of a layer, so W is
+// staged one 32-wide k slice (all 256 output rows) at a time and the GELU epilogue
+// runs once per layer.  256 registers per lane give two waves per SIMD (two
+// work-groups per CU), so one group's epilogue overlaps the other's MFMAs.
 // ---------------------------------------------------------------------------
 constexpr int FROWS = 128;             // rows per work-group
-constexpr int INFER_RT = 2;            // row tiles of 16 per wave (4 waves per work-group)
-constexpr int FLDS = H + 8;            // padded row of a staged W tile (bf16)
+constexpr int INFER_RT = 2;            // row tiles of 16 per wave
+constexpr int INFER_BT = 256;          // 4 waves per work-group
+constexpr int SK = 32 + 8;             // padded row of a staged k slice (bf16)
+constexpr int NSLICE = 16;             // k slices of the two 256 x 256 layers
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
@@ -413,120 +419,117 @@ __device__ __forceinline__ int perm_feature(int s, int g, int j)
     return 32 * s + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
 }
 
-// RT row tiles of 16 per wave; 128 / (16 RT) waves per work-group.
-template <int RT>
-__global__ void __launch_bounds__(64 * 8 / RT) k_mlp_infer(const float *x, uint64_t rows, const bf16_t *wbf,
+__global__ void __launch_bounds__(INFER_BT, 2) k_mlp_infer(const float *x, uint64_t rows, const bf16_t *wbf,
                                                            const float *params, float *y, uint64_t y_stride)
 {
-    constexpr int BT = 64 * 8 / RT;                      // threads per work-group
-    __shared__ __align__(16) bf16_t sW[3][16 * FLDS];
+    constexpr int RT = INFER_RT, BT = INFER_BT;
+    static_assert(BT == H, "thread t fills the small tables' entries of feature t");
+    static_assert(BT / 64 * 16 * RT == FROWS, "the waves cover the group's rows");
+    __shared__ __align__(16) bf16_t sW[3][H * SK];
     __shared__ __align__(16) float sL1[H * 8];          // per feature: W1[f][0..4], b1[f], pad
-    __shared__ float sB[2][H], sW4[H];
+    __shared__ __align__(16) float sB[2][H];
+    __shared__ float sW4[H];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 4, c = lane & 15;
     const int m = blockIdx.y;
     const float *P = params + (uint64_t)m * NPARAM;
     const bf16_t *WB = wbf + (uint64_t)m * NBF;
-    if (t < H) {
 #pragma unroll
-        for (int j = 0; j < IN; ++j) sL1[t * 8 + j] = bf2f(WB[BOFF_W1 + t * IN + j]);
-        sL1[t * 8 + 5] = P[OFF_B1 + t];
-        sB[0][t] = P[OFF_B2 + t];
-        sB[1][t] = P[OFF_B3 + t];
-        sW4[t] = bf2f(WB[BOFF_W4 + t]);
-    }
+    for (int j = 0; j < IN; ++j) sL1[t * 8 + j] = bf2f(WB[BOFF_W1 + t * IN + j]);
+    sL1[t * 8 + 5] = P[OFF_B1 + t];
+    sB[0][t] = P[OFF_B2 + t];
+    sB[1][t] = P[OFF_B3 + t];
+    sW4[t] = bf2f(WB[BOFF_W4 + t]);
 
-    // staging of W tile ft (rows 16 ft .. 16 ft + 15, all 256 k) in 16-byte units:
-    // unit u = t + i BT is row u / 32, columns 8 (u % 32) .. + 7
-    constexpr int UNITS = 16 * H / 8 / BT;
-    auto load_tile = [&](const bf16_t *W, int ft, uint4 (&v)[UNITS]) {
+    // slice T: layer 2 + T / 8, k columns 32 (T % 8) .. + 31 of all 256 rows, in
+    // 16-byte units: unit u = t + i BT is row u / 4, columns 8 (u % 4) .. + 7
+    constexpr int UNITS = H * 32 / 8 / BT;
+    auto load_slice = [&](int T, uint4 (&v)[UNITS]) {
+        const bf16_t *W = WB + (T < 8 ? BOFF_W2 : BOFF_W3) + 32 * (T & 7);
 #pragma unroll
         for (int i = 0; i < UNITS; ++i) {
             const int u = t + i * BT;
-            v[i] = *reinterpret_cast<const uint4 *>(W + (uint64_t)(16 * ft + (u >> 5)) * H + (u & 31) * 8);
+            v[i] = *reinterpret_cast<const uint4 *>(W + (uint64_t)(u >> 2) * H + (u & 3) * 8);
         }
     };
-    auto store_tile = [&](int buf, const uint4 (&v)[UNITS]) {
+    auto store_slice = [&](int buf, const uint4 (&v)[UNITS]) {
 #pragma unroll
         for (int i = 0; i < UNITS; ++i) {
             const int u = t + i * BT;
-            *reinterpret_cast<uint4 *>(&sW[buf][(u >> 5) * FLDS + (u & 31) * 8]) = v[i];
+            *reinterpret_cast<uint4 *>(&sW[buf][(u >> 2) * SK + (u & 3) * 8]) = v[i];
         }
     };
     uint4 pv[UNITS];
-    load_tile(WB + BOFF_W2, 0, pv);
-    store_tile(0, pv);
-    load_tile(WB + BOFF_W2, 1, pv);
-    store_tile(1, pv);
+    load_slice(0, pv);
+    store_slice(0, pv);
+    load_slice(1, pv);
+    store_slice(1, pv);
     __syncthreads();
 
-    // ---- layer 1 (5 -> 256, FP32 FMA on the BF16 weights) into B operands ----
+    // ---- layer 1 (5 -> 256, FP32 FMA on the BF16 weights) into B operands; each
+    //      weight row read from LDS once for both row tiles ----
     const uint64_t base = (uint64_t)blockIdx.x * FROWS + (uint64_t)wave * 16 * RT;
     bf16x8 act[RT][8];
+    float u[RT][IN];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
         const uint64_t r = base + 16 * rt + c;
-        float u[IN];
-        normalise(x + (r < rows ? r : 0) * IN, u);
+        normalise(x + (r < rows ? r : 0) * IN, u[rt]);
+    }
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
+    for (int s = 0; s < 8; ++s) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const float *w = &sL1[perm_feature(s, g, j) * 8];
-                float z = w[5];
+        for (int j = 0; j < 8; ++j) {
+            const float *w = &sL1[perm_feature(s, g, j) * 8];
+            const float4 w03 = *reinterpret_cast<const float4 *>(w);
+            const float2 w45 = *reinterpret_cast<const float2 *>(w + 4);
 #pragma unroll
-                for (int i = 0; i < IN; ++i) z = fmaf(w[i], u[i], z);
+            for (int rt = 0; rt < RT; ++rt) {
+                float z = w45.y;
+                z = fmaf(w03.x, u[rt][0], z);
+                z = fmaf(w03.y, u[rt][1], z);
+                z = fmaf(w03.z, u[rt][2], z);
+                z = fmaf(w03.w, u[rt][3], z);
+                z = fmaf(w45.x, u[rt][4], z);
                 act[rt][s][j] = to_bf(gelu(z));
             }
         }
     }
 
-    // ---- layers 2 and 3 on MFMA ----
-    // Software pipeline over the 32 W tiles of the two layers (tile T: layer T / 16,
-    // output rows 16 (T % 16) ..): the MFMAs of tile T + 1 are issued before the
-    // GELU epilogue of tile T, so matrix cores and VALU overlap.  Tile T lives in LDS
-    // buffer T % 3; tile T + 2 is fetched from global memory during iteration T and
-    // stored after its epilogue into the buffer tile T - 1 used, which every wave
-    // finished reading before the barrier that ended iteration T - 2.  One barrier
-    // per iteration also publishes tile T + 2 before iteration T + 1 reads it.
-    auto mma_tile = [&](int buf, floatx4 (&acc)[RT]) {
+    // ---- layers 2 and 3 on MFMA, k slice by k slice ----
+    // Slice T lives in LDS buffer T % 3; slice T + 2 is fetched from global memory
+    // during iteration T and stored at its end into the buffer slice T - 1 used,
+    // which every wave finished reading before the barrier that ended iteration
+    // T - 1.  That barrier also published slice T + 1 before iteration T + 1 reads it.
+    floatx4 acc[16][RT];
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
-        const bf16_t *wrow = &sW[buf][c * FLDS];
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            const bf16x4 lo = *reinterpret_cast<const bf16x4 *>(wrow + 32 * s + 4 * g);
-            const bf16x4 hi = *reinterpret_cast<const bf16x4 *>(wrow + 32 * s + 16 + 4 * g);
-            const bf16x8 a = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[rt][s], acc[rt], 0, 0, 0);
-        }
-    };
-#pragma unroll
-    for (int layer = 0; layer < 2; ++layer) {
-        bf16x8 nxt[RT][8];
-        floatx4 acc[2][RT];
-        mma_tile((16 * layer) % 3, acc[0]);
+    for (int T = 0; T < NSLICE; ++T) {
+        const int s = T & 7;
+        if (T + 2 < NSLICE) load_slice(T + 2, pv);
+        const bf16_t *sl = &sW[T % 3][c * SK];
 #pragma unroll
         for (int ft = 0; ft < 16; ++ft) {
-            const int T = 16 * layer + ft;
-            if (T + 2 < 32) load_tile(WB + ((T + 2) < 16 ? BOFF_W2 : BOFF_W3), (T + 2) & 15, pv);
-            if (ft + 1 < 16) mma_tile((T + 1) % 3, acc[(ft + 1) & 1]);
-            // epilogue of tile T: acc[rt][i] = Z^T[16 ft + 4 g + i][row c of tile rt]
-            // -> next layer's slot (k-step ft / 2, j = 4 (ft % 2) + i)
+            const bf16x4 lo = *reinterpret_cast<const bf16x4 *>(sl + 16 * ft * SK + 4 * g);
+            const bf16x4 hi = *reinterpret_cast<const bf16x4 *>(sl + 16 * ft * SK + 16 + 4 * g);
+            const bf16x8 a = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+            // the accumulators start at the bias of their output features
+            const floatx4 bias = *reinterpret_cast<const floatx4 *>(&sB[T >> 3][16 * ft + 4 * g]);
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    nxt[rt][ft >> 1][4 * (ft & 1) + i] =
-                        to_bf(gelu(acc[ft & 1][rt][i] + sB[layer][16 * ft + 4 * g + i]));
-            if (T + 2 < 32) store_tile((T + 2) % 3, pv);
-            __syncthreads();
+                acc[ft][rt] =
+                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[rt][s], s == 0 ? bias : acc[ft][rt], 0, 0, 0);
         }
+        if (s == 7) {
+            // epilogue: acc[ft][rt][i] = Z^T[16 ft + 4 g + i][row c of tile rt] -> the
+            // next layer's slot (k-step ft / 2, j = 4 (ft % 2) + i)
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
+            for (int ft = 0; ft < 16; ++ft)
 #pragma unroll
-            for (int s = 0; s < 8; ++s) act[rt][s] = nxt[rt][s];
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) act[rt][ft >> 1][4 * (ft & 1) + i] = to_bf(gelu(acc[ft][rt][i]));
+        }
+        if (T + 2 < NSLICE) store_slice((T + 2) % 3, pv);
+        __syncthreads();
     }
 
     // ---- layer 4 (256 -> 1): partial dot per lane group, then across the 4 groups ----
@@ -636,8 +639,8 @@ extern "C" int bm_mlp_forward(uint32_t n_members, const float *d_params, const u
     rc = check_device(&dev);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_mlp_infer<INFER_RT>, dim3((uint32_t)((batch + FROWS - 1) / FROWS), n_members),
-                       dim3(64 * 8 / INFER_RT), 0, s, d_x, batch, (const bf16_t *)d_wbf, d_params, d_y, batch);
+    hipLaunchKernelGGL(k_mlp_infer, dim3((uint32_t)((batch + FROWS - 1) / FROWS), n_members), dim3(INFER_BT), 0,
+                       s, d_x, batch, (const bf16_t *)d_wbf, d_params, d_y, batch);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? ok() : hip_fail(e, "bm_mlp_forward");
 }
@@ -747,8 +750,8 @@ static hipError_t enqueue_query(uint32_t n_members, const float *d_params, const
                                 uint32_t *d_fallback_idx, uint32_t *d_fallback_count, float *y, uint32_t *blk,
                                 hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mlp_infer<INFER_RT>, dim3((uint32_t)((batch + FROWS - 1) / FROWS), n_members),
-                       dim3(64 * 8 / INFER_RT), 0, s, d_x, batch, (const bf16_t *)d_wbf, d_params, y, batch);
+    hipLaunchKernelGGL(k_mlp_infer, dim3((uint32_t)((batch + FROWS - 1) / FROWS), n_members), dim3(INFER_BT), 0,
+                       s, d_x, batch, (const bf16_t *)d_wbf, d_params, y, batch);
     hipError_t e = hipGetLastError();
     const uint64_t nblk = (batch + 255) / 256;
     if (e == hipSuccess) {

@@ -17,14 +17,16 @@ from . import workloads as W
 SPP = 200      # steps per drive period of the inertial model
 
 
-def point_workloads(x: np.ndarray, n_paths: int, periods: int, seed: int = 0, first_point: int = 0):
-    """Inertial-model workloads (Gaussian noise, FP32 paths) for rows x = (a, omega, F, D, gamma)."""
+def point_workloads(x: np.ndarray, n_paths, periods: int, seed: int = 0, first_point: int = 0):
+    """Inertial-model workloads (Gaussian noise, FP32 paths) for rows x = (a, omega, F, D, gamma);
+    n_paths is one count for every row or one per row."""
     out = []
     n_steps = periods * SPP
+    counts = np.broadcast_to(np.asarray(n_paths, dtype=np.int64), (len(x),))
     for i, r in enumerate(np.asarray(x, dtype=np.float64)):
         out.append(W.Workload(name="q%d" % i, dyn=W.INERTIAL, pot=W.POT_SIN, noise=W.GAUSS, prec=W.F32,
                               a=float(r[0]), omega=float(r[1]), F=float(r[2]), D=float(r[3]),
-                              gamma=float(r[4]), spp=SPP, n_paths=n_paths, n_steps=n_steps,
+                              gamma=float(r[4]), spp=SPP, n_paths=int(counts[i]), n_steps=n_steps,
                               n_window=n_steps // 2, seed=seed, point=first_point + i, x0_lo=0.0, x0_hi=1.0,
                               v0_lo=-2.0, v0_hi=2.0))
     return out
@@ -37,11 +39,23 @@ class MCResult:
     std: np.ndarray
     seconds: float
     path_steps: int
+    n_paths: np.ndarray | None = None
 
 
-def monte_carlo(x: np.ndarray, n_paths: int, periods: int, seed: int = 0, first_point: int = 0,
+def pool(n1, m1, s1, n2, m2, s2):
+    """Count, mean and sample standard deviation of two samples taken together, from
+    each one's count, mean and sample standard deviation (arrays, elementwise)."""
+    n1, n2 = np.asarray(n1, dtype=np.float64), np.asarray(n2, dtype=np.float64)
+    n = n1 + n2
+    mean = (n1 * m1 + n2 * m2) / n
+    ss = (n1 - 1.0) * np.square(s1) + (n2 - 1.0) * np.square(s2) + n1 * n2 / n * np.square(m1 - m2)
+    return n, mean, np.sqrt(ss / (n - 1.0))
+
+
+def monte_carlo(x: np.ndarray, n_paths, periods: int, seed: int = 0, first_point: int = 0,
                 tune=None) -> MCResult:
-    """<v> of every row by one batched scan (plan + one graph launch)."""
+    """<v> of every row by one batched scan (plan + one graph launch); n_paths is one
+    count for every row or one per row."""
     import torch
     pts = point_workloads(x, n_paths, periods, seed, first_point)
     mr = [W.to_c(w) for w in pts]
@@ -55,7 +69,37 @@ def monte_carlo(x: np.ndarray, n_paths: int, periods: int, seed: int = 0, first_
     mean = np.array([s.mean for s in st])
     se = np.array([s.se for s in st])
     std = np.array([math.sqrt(s.var) if s.n > 1 else float("nan") for s in st])
-    return MCResult(mean, se, std, el, sum(w.path_steps() for w in pts))
+    counts = np.array([w.n_paths for w in pts], dtype=np.int64)
+    return MCResult(mean, se, std, el, sum(w.path_steps() for w in pts), counts)
+
+
+def adaptive_monte_carlo(x: np.ndarray, tol: float, periods: int, pilot: int = 64, max_paths: int = 1 << 16,
+                         rounds: int = 4, seed: int = 0, first_point: int = 0, tune=None) -> MCResult:
+    """<v> of every row at 3 SE <= tol by sequential sampling: a pilot scan of `pilot`
+    paths per row, then up to rounds - 1 top-up scans.  Before each top-up, row i's
+    spread s_i (of all its paths so far) sets its total N_i = ceil((3 s_i / tol)^2),
+    at most max_paths (a row without a finite spread takes max_paths); rows short of
+    N_i run the difference on streams of their own (seed + round), and the samples are
+    pooled.  Seconds and path-steps count every scan."""
+    x = np.asarray(x)
+    res = monte_carlo(x, pilot, periods, seed, first_point, tune)
+    n = res.n_paths.astype(np.float64)
+    mean, std = res.mean.copy(), res.std.copy()
+    seconds, path_steps = res.seconds, res.path_steps
+    for rd in range(1, rounds):
+        sd = np.where(np.isfinite(std), std, np.inf)
+        need = np.ceil(np.square(3.0 * sd / tol))
+        need = np.minimum(np.nan_to_num(need, nan=float(max_paths), posinf=float(max_paths)), max_paths)
+        more = np.nonzero(need > n)[0]
+        if not len(more):
+            break
+        top = monte_carlo(x[more], (need[more] - n[more]).astype(np.int64), periods, seed + rd, first_point, tune)
+        n2, m2, s2 = pool(n[more], mean[more], std[more], top.n_paths, top.mean, top.std)
+        n[more], mean[more], std[more] = n2, m2, s2
+        seconds += top.seconds
+        path_steps += top.path_steps
+    se = std / np.sqrt(n)
+    return MCResult(mean, se, std, seconds, path_steps, n.astype(np.int64))
 
 
 def train(sur: "B.Surrogate", x: np.ndarray, y: np.ndarray, epochs: int, batch: int = 1024, lr: float = 1e-3,
@@ -112,8 +156,11 @@ class QueryResult:
     t_fallback: float
 
 
-def query(sur: "B.Surrogate", x: np.ndarray, threshold: float, n_paths: int, periods: int,
-          seed: int = 0, mc_first_point: int = 1 << 30) -> QueryResult:
+def query(sur: "B.Surrogate", x: np.ndarray, threshold: float, n_paths: int | None, periods: int,
+          seed: int = 0, mc_first_point: int = 1 << 30, tol: float | None = None) -> QueryResult:
+    """Surrogate mean for every row; rows whose ensemble spread exceeds `threshold` are
+    answered by Monte Carlo instead: n_paths paths each, or, with tol, the sequential
+    budget of adaptive_monte_carlo (3 SE <= tol)."""
     import torch
     xd = torch.tensor(np.asarray(x, dtype=np.float32), device=sur.device)
     torch.cuda.synchronize()
@@ -126,7 +173,10 @@ def query(sur: "B.Surrogate", x: np.ndarray, threshold: float, n_paths: int, per
     value = mean.cpu().numpy().astype(np.float64)
     t_fb = 0.0
     if n_fb:
-        mc = monte_carlo(np.asarray(x)[fb], n_paths, periods, seed, mc_first_point)
+        if tol is not None:
+            mc = adaptive_monte_carlo(np.asarray(x)[fb], tol, periods, seed=seed, first_point=mc_first_point)
+        else:
+            mc = monte_carlo(np.asarray(x)[fb], n_paths, periods, seed, mc_first_point)
         value[fb] = mc.mean
         t_fb = mc.seconds
     return QueryResult(value, std.cpu().numpy(), fb, t1 - t0, t_fb)

@@ -110,3 +110,27 @@ def test_surrogate_on_the_configured_domain_is_tracked():
            float(np.mean(cost[~keep])) / float(np.mean(cost)) if f > 0 else 0.0, gain))
     assert keep.mean() > 0.3
     assert np.percentile(err[keep], 95) <= tol
+
+
+def test_adaptive_monte_carlo_meets_its_tolerance():
+    """The fallback's sequential budget: every point gets at least the pilot's paths and
+    at most the cap, the path-steps charged are the paths run, the pooled standard
+    errors meet 3 SE <= tol (up to the spread the last round misjudged), and the means
+    agree with an independent scan of 16384 paths per point."""
+    tol, periods, pilot, cap = 0.02, 50, 64, 1 << 15
+    x = W.surrogate_queries(64, seed=31)
+    ad = S.adaptive_monte_carlo(x, tol, periods, pilot=pilot, max_paths=cap, seed=3, first_point=1 << 26)
+    assert np.all(ad.n_paths >= pilot) and np.all(ad.n_paths <= cap)
+    assert ad.path_steps == int(np.sum(ad.n_paths)) * periods * S.SPP
+    free = ad.n_paths < cap
+    say("adaptive: paths per point %d .. %d (median %d), %d capped, 3 SE / tol max %.2f, %.3f s"
+        % (ad.n_paths.min(), ad.n_paths.max(), np.median(ad.n_paths), (~free).sum(),
+           np.max(3 * ad.se[free] / tol) if free.any() else 0.0, ad.seconds))
+    assert np.mean(3 * ad.se[free] <= tol) >= 0.9
+    assert np.all(3 * ad.se[free] <= 1.5 * tol)
+    truth = S.monte_carlo(x, 1 << 14, periods, seed=9, first_point=1 << 26)
+    z = np.abs(ad.mean - truth.mean) / np.sqrt(ad.se ** 2 + truth.se ** 2)
+    say("adaptive vs truth: max z %.2f, fraction within 3 combined SE %.3f" % (z.max(), np.mean(z <= 3)))
+    assert np.mean(z <= 3) >= 0.95
+    # the budget follows the spread: a uniform count at the largest need costs more
+    assert np.sum(ad.n_paths) < len(x) * np.max(ad.n_paths)
