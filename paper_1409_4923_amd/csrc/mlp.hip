@@ -407,7 +407,7 @@ GemmArgs gemm_args()
 constexpr int FROWS = 128;             // rows per work-group
 constexpr int INFER_RT = 2;            // row tiles of 16 per wave
 constexpr int INFER_BT = 256;          // 4 waves per work-group
-constexpr int SK = 32 + 8;             // padded row of a staged k slice (bf16)
+constexpr int SK = 32;                 // row of a staged k slice (bf16), 8-byte units swizzled
 constexpr int NSLICE = 16;             // k slices of the two 256 x 256 layers
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -451,11 +451,34 @@ __global__ void __launch_bounds__(INFER_BT, 2) k_mlp_infer(const float *x, uint6
             v[i] = *reinterpret_cast<const uint4 *>(W + (uint64_t)(u >> 2) * H + (u & 3) * 8);
         }
     };
+    // In LDS, 8-byte unit p (k columns 4p .. 4p + 3) of row r sits at position
+    // p ^ ((r >> 1) & 7): the 16 rows a fragment read touches then hit 16 different
+    // bank pairs for every lane group (no bank conflicts).  Inside the k loop a slice
+    // is staged in two halves of UNITS / 2 units per thread.
+    auto load_half = [&](int T, int hf, uint4 (&v)[UNITS / 2]) {
+        const bf16_t *W = WB + (T < 8 ? BOFF_W2 : BOFF_W3) + 32 * (T & 7);
+#pragma unroll
+        for (int i = 0; i < UNITS / 2; ++i) {
+            const int u = t + (i + hf * UNITS / 2) * BT;
+            v[i] = *reinterpret_cast<const uint4 *>(W + (uint64_t)(u >> 2) * H + (u & 3) * 8);
+        }
+    };
+    auto store_half = [&](int buf, int hf, const uint4 (&v)[UNITS / 2]) {
+#pragma unroll
+        for (int i = 0; i < UNITS / 2; ++i) {
+            const int u = t + (i + hf * UNITS / 2) * BT;
+            const int r = u >> 2, q = u & 3, h = (r >> 1) & 7;
+            *reinterpret_cast<uint2 *>(&sW[buf][r * SK + ((2 * q) ^ h) * 4]) = uint2{v[i].x, v[i].y};
+            *reinterpret_cast<uint2 *>(&sW[buf][r * SK + ((2 * q + 1) ^ h) * 4]) = uint2{v[i].z, v[i].w};
+        }
+    };
     auto store_slice = [&](int buf, const uint4 (&v)[UNITS]) {
 #pragma unroll
         for (int i = 0; i < UNITS; ++i) {
             const int u = t + i * BT;
-            *reinterpret_cast<uint4 *>(&sW[buf][(u >> 2) * SK + (u & 3) * 8]) = v[i];
+            const int r = u >> 2, q = u & 3, h = (r >> 1) & 7;
+            *reinterpret_cast<uint2 *>(&sW[buf][r * SK + ((2 * q) ^ h) * 4]) = uint2{v[i].x, v[i].y};
+            *reinterpret_cast<uint2 *>(&sW[buf][r * SK + ((2 * q + 1) ^ h) * 4]) = uint2{v[i].z, v[i].w};
         }
     };
     uint4 pv[UNITS];
@@ -497,19 +520,30 @@ __global__ void __launch_bounds__(INFER_BT, 2) k_mlp_infer(const float *x, uint6
 
     // ---- layers 2 and 3 on MFMA, k slice by k slice ----
     // Slice T lives in LDS buffer T % 3; slice T + 2 is fetched from global memory
-    // during iteration T and stored at its end into the buffer slice T - 1 used,
-    // which every wave finished reading before the barrier that ended iteration
+    // during iteration T, half after half, and stored into the buffer slice T - 1
+    // used, which every wave finished reading before the barrier that ended iteration
     // T - 1.  That barrier also published slice T + 1 before iteration T + 1 reads it.
     floatx4 acc[16][RT];
 #pragma unroll
     for (int T = 0; T < NSLICE; ++T) {
         const int s = T & 7;
-        if (T + 2 < NSLICE) load_slice(T + 2, pv);
-        const bf16_t *sl = &sW[T % 3][c * SK];
+        uint4 ph[UNITS / 2];
+        if (T + 2 < NSLICE) load_half(T + 2, 0, ph);
+        // The MFMA block runs at raised wave priority, so the scheduler keeps the
+        // matrix cores fed from this wave while the other group's wave on the SIMD
+        // works through its VALU epilogue.
+        __builtin_amdgcn_s_setprio(1);
+        // lane (g, c) reads units g and 4 + g of rows 16 ft + c
+        const bf16_t *slo = &sW[T % 3][c * SK + 4 * (g ^ ((c >> 1) & 7))];
+        const bf16_t *shi = &sW[T % 3][c * SK + 4 * ((g ^ ((c >> 1) & 7)) ^ 4)];
 #pragma unroll
         for (int ft = 0; ft < 16; ++ft) {
-            const bf16x4 lo = *reinterpret_cast<const bf16x4 *>(sl + 16 * ft * SK + 4 * g);
-            const bf16x4 hi = *reinterpret_cast<const bf16x4 *>(sl + 16 * ft * SK + 16 + 4 * g);
+            if (ft == 8 && T + 2 < NSLICE) {
+                store_half((T + 2) % 3, 0, ph);
+                load_half(T + 2, 1, ph);
+            }
+            const bf16x4 lo = *reinterpret_cast<const bf16x4 *>(slo + 16 * ft * SK);
+            const bf16x4 hi = *reinterpret_cast<const bf16x4 *>(shi + 16 * ft * SK);
             const bf16x8 a = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
             // the accumulators start at the bias of their output features
             const floatx4 bias = *reinterpret_cast<const floatx4 *>(&sB[T >> 3][16 * ft + 4 * g]);
@@ -518,6 +552,7 @@ __global__ void __launch_bounds__(INFER_BT, 2) k_mlp_infer(const float *x, uint6
                 acc[ft][rt] =
                     __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[rt][s], s == 0 ? bias : acc[ft][rt], 0, 0, 0);
         }
+        __builtin_amdgcn_s_setprio(0);
         if (s == 7) {
             // epilogue: acc[ft][rt][i] = Z^T[16 ft + 4 g + i][row c of tile rt] -> the
             // next layer's slot (k-step ft / 2, j = 4 (ft % 2) + i)
@@ -528,7 +563,7 @@ __global__ void __launch_bounds__(INFER_BT, 2) k_mlp_infer(const float *x, uint6
 #pragma unroll
                     for (int i = 0; i < 4; ++i) act[rt][ft >> 1][4 * (ft & 1) + i] = to_bf(gelu(acc[ft][rt][i]));
         }
-        if (T + 2 < NSLICE) store_slice((T + 2) % 3, pv);
+        if (T + 2 < NSLICE) store_half((T + 2) % 3, 1, ph);
         __syncthreads();
     }
 
