@@ -523,6 +523,28 @@ def surrogate_leg(args):
     # the largest the held-out points need; the fallback then pays the same.
     fixed_cost = float(np.max(need)) * n_steps / rate
     sur_rate_fixed = delivered / (t_query + f * n_q * fixed_cost)
+    # A threshold calibrated on held-out data instead of fixed: on the even-indexed
+    # held-out points, the largest threshold on a grid whose answered points keep a p95
+    # error <= tol and 95% within tol; judged on the odd-indexed points (fallback cost
+    # and accuracy) and on the 10^6 queries (fallback fraction).
+    cal_a, cal_b = np.arange(0, len(xh), 2), np.arange(1, len(xh), 2)
+    thr_cal, sweep = S.calibrate_threshold(std[cal_a], err[cal_a], tol, [thr * 2.0 ** (k / 4.0) for k in range(17)])
+    thr_cal = thr if thr_cal is None else thr_cal
+    kb = std[cal_b] <= thr_cal
+    good_b = float(np.mean(err[cal_b][kb] <= tol)) if kb.any() else 0.0
+    fb_cost_b = float(np.mean(cost[cal_b][~kb])) if (~kb).any() else mc_cost
+    _, _, _, qc = sur.query(xq, thr_cal)
+    f_cal = int(qc.item()) / n_q
+    deliv_cal = n_q * ((1.0 - f_cal) * good_b + f_cal)
+    t_sur_cal = t_query + f_cal * n_q * fb_cost_b
+    calibrated = {"threshold": thr_cal, "sweep_even_half": sweep, "fallback_fraction": f_cal,
+                  "answered_odd_half": float(kb.mean()),
+                  "abs_err_answered_p95_odd_half": float(np.percentile(err[cal_b][kb], 95)) if kb.any() else None,
+                  "within_tol_answered_odd_half": good_b,
+                  "gain": deliv_cal / t_sur_cal * mc_cost,
+                  "gain_amortised": deliv_cal / (t_sur_cal + t_label + t_train) * mc_cost}
+    print("surrogate: calibrated threshold %.4f: fallback %.3f, gain %.3f" % (thr_cal, f_cal, calibrated["gain"]),
+          file=sys.stderr, flush=True)
     # Both sides as run, without knowing sigma_i: sequential MC (a 64-path pilot, then
     # up to three top-ups sized from the spread so far) on every held-out point gives
     # plain MC's cost per point; the same runs on the points the ensemble routes give
@@ -562,6 +584,7 @@ def surrogate_leg(args):
             "fixed_n_paths": float(np.max(need)), "mc_points_per_s_fixed_n": 1.0 / fixed_cost,
             "gain_vs_fixed_n": sur_rate_fixed * fixed_cost,
             "adaptive_fallback": adaptive,
+            "calibrated_threshold": calibrated,
             "mlp_inference": {"achieved": flops / t_query / 1e12, "peak": 2500.0, "unit": "TFLOP/s (BF16 MFMA)",
                               "frac": flops / t_query / 2.5e15}}
 

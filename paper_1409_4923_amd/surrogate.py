@@ -147,6 +147,24 @@ def uncertain_points(sur: "B.Surrogate", x: np.ndarray, n_pick: int, threshold: 
     return np.sort(over)
 
 
+def calibrate_threshold(std: np.ndarray, err: np.ndarray, tol: float, grid, within: float = 0.95):
+    """Largest routing threshold t of `grid` (ascending) at which the points the
+    ensemble would answer (spread std <= t) keep a 95th-percentile error <= tol and a
+    fraction `within` of them within tol, judged on calibration points with known
+    errors err = |surrogate - truth|; None if no t qualifies.  Also returns the sweep
+    (threshold, answered fraction, p95, fraction within tol) for every t."""
+    std, err = np.asarray(std), np.asarray(err)
+    best, sweep = None, []
+    for t in grid:
+        k = std <= t
+        p95 = float(np.percentile(err[k], 95)) if k.any() else None
+        w = float(np.mean(err[k] <= tol)) if k.any() else None
+        sweep.append({"threshold": float(t), "answered": float(k.mean()), "p95": p95, "within_tol": w})
+        if p95 is not None and p95 <= tol and w >= within:
+            best = float(t)
+    return best, sweep
+
+
 @dataclass
 class QueryResult:
     value: np.ndarray          # surrogate mean, replaced by Monte Carlo where routed

@@ -16,3 +16,20 @@ def test_pool_equals_statistics_of_the_joined_sample():
         assert np.all(n == n1 + n2)
         np.testing.assert_allclose(m, j.mean(1), rtol=0, atol=1e-14)
         np.testing.assert_allclose(s, j.std(1, ddof=1), rtol=1e-12)
+
+
+def test_calibrate_threshold_picks_the_largest_qualifying_threshold():
+    rng = np.random.default_rng(3)
+    std = rng.uniform(0.0, 0.04, 20000)
+    err = np.abs(rng.normal(0.0, 1.0, 20000)) * std     # error grows with the spread
+    tol = 0.01
+    grid = [0.0025 * 2.0 ** (k / 4.0) for k in range(13)]
+    t, sweep = S.calibrate_threshold(std, err, tol, grid)
+    assert t is not None and t in grid
+    for row in sweep:
+        ok = row["p95"] is not None and row["p95"] <= tol and row["within_tol"] >= 0.95
+        assert ok == (row["threshold"] <= t)             # the qualifying thresholds are a prefix here
+        k = std <= row["threshold"]
+        assert row["answered"] == k.mean()
+    assert t < grid[-1]                                  # the largest spreads do not qualify
+    assert S.calibrate_threshold(std, err, 1e-6, grid)[0] is None
