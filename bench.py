@@ -428,6 +428,38 @@ def infer_leg(args):
             "frac": flops / best / 1e9 / 2500.0}
 
 
+def train_leg(args):
+    """One training step of the 5-member ensemble (backward of the MSE + Adam) on
+    minibatches of 1024 and 4096 rows drawn from 10^5 rows: 10 untimed steps, then 200
+    timed with HIP events (ms per step)."""
+    import numpy as np
+    import torch
+    from paper_1409_4923_amd import bmotor as B
+    from paper_1409_4923_amd import workloads as W
+    sur = B.Surrogate(5, seed=7)
+    n = 100_000
+    x = torch.tensor(W.surrogate_queries(n, seed=1), device="cuda")
+    y = torch.tensor(np.random.default_rng(2).normal(0.0, 0.01, n).astype(np.float32), device="cuda")
+    rng = np.random.default_rng(0)
+    out = {}
+    for batch in (1024, 4096):
+        idx = torch.tensor(rng.integers(0, n, (210, 5, batch)).astype(np.int32), device="cuda")
+        for s in range(10):
+            sur.backward(x, y, idx[s])
+            sur.adam(1e-3)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for s in range(10, 210):
+            sur.backward(x, y, idx[s])
+            sur.adam(1e-3)
+        e1.record()
+        torch.cuda.synchronize()
+        out["ms_per_step_batch_%d" % batch] = e0.elapsed_time(e1) / 200
+    out["members"] = 5
+    return out
+
+
 def surrogate_leg(args):
     """Learned surrogate of <v>(a, omega, F, D, gamma) with Monte Carlo fallback.
 
@@ -601,8 +633,8 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="c3,c2jump,scan,scheme,infer,surrogate",
-                    help="extra legs: c3, c2jump, scan, scheme, infer, surrogate (or none)")
+    ap.add_argument("--legs", default="c3,c2jump,scan,scheme,train,infer,surrogate",
+                    help="extra legs: c3, c2jump, scan, scheme, train, infer, surrogate (or none)")
     ap.add_argument("--labels", type=int, default=60_000, help="uniform labels before active learning")
     ap.add_argument("--active-rounds", type=int, default=0,
                     help="rounds of labels where the ensemble disagrees most (measured to raise the fallback "
@@ -717,6 +749,8 @@ def main():
         rec["scan"] = scan_leg(args)
     if "scheme" in legs:
         rec["scheme"] = scheme_leg(args)
+    if "train" in legs:
+        rec["train"] = train_leg(args)
     if "infer" in legs:
         rec["infer"] = infer_leg(args)
     if "surrogate" in legs:

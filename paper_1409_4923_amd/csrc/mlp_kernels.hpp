@@ -142,8 +142,19 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+    // LDS tiles are row-major (row = m of A, n of B) with k along the row; the
+    // 16-byte units of 8 k are XOR-swizzled by the row's group of 8, so that the
+    // transposing writes below spread over all banks (the fragment reads stay
+    // conflict-free: a unit is still read whole).
+    auto lds = [](int row, int k) { return row * LK + ((((k >> 3) ^ ((row >> 3) & (TKT / 8 - 1)))) << 3) + (k & 7); };
     for (int k0 = kbeg; k0 < kend; k0 += TKT) {
-        // ---- stage A (64 x TKT) and B (TKT x 64, stored n-major), 32 k at a time ----
+        // ---- stage A (64 x TKT) and B (TKT x 64, stored n-major) ----
+        // An operand whose rows run along k arrives in 16-byte units of 8 k: thread t
+        // loads unit t % 4 of row t / 4 for each 32-wide k slice.  A transposed operand
+        // (rows along m or n) arrives in units of 8 rows at one k: with TKT >= 64 thread
+        // t loads rows 8 (t % 8) .. + 7 at the KS consecutive k = KS (t / 8) + r and
+        // writes them transposed (KS k of a row in one write), else one k per thread
+        // and eight 2-byte writes.
         uint4 va[KS], vb[KS];
 #pragma unroll
         for (int sl = 0; sl < KS; ++sl) {
@@ -153,36 +164,67 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
                 const int r = t >> 2, kq = (t & 3) * 8;
                 if (m0 + r < g.M) va[sl] = *reinterpret_cast<const uint4 *>(A + (uint64_t)(m0 + r) * g.lda + kb + kq);
             } else {
-                const int kk = t >> 3, mc = (t & 7) * 8;
-                if (m0 + mc < g.M) va[sl] = *reinterpret_cast<const uint4 *>(A + (uint64_t)(kb + kk) * g.lda + m0 + mc);
+                const int kk = KS > 1 ? KS * (t >> 3) + sl : (t >> 3), mc = (t & 7) * 8;
+                if (m0 + mc < g.M)
+                    va[sl] = *reinterpret_cast<const uint4 *>(A + (uint64_t)(KS > 1 ? k0 + kk : kb + kk) * g.lda + m0 + mc);
             }
             if (!TB) {
                 const int c = t >> 2, kq = (t & 3) * 8;
                 vb[sl] = *reinterpret_cast<const uint4 *>(B + (uint64_t)(n0 + c) * g.ldb + kb + kq);
             } else {
-                const int kk = t >> 3, nc = (t & 7) * 8;
-                vb[sl] = *reinterpret_cast<const uint4 *>(B + (uint64_t)(kb + kk) * g.ldb + n0 + nc);
+                const int kk = KS > 1 ? KS * (t >> 3) + sl : (t >> 3), nc = (t & 7) * 8;
+                vb[sl] = *reinterpret_cast<const uint4 *>(B + (uint64_t)(KS > 1 ? k0 + kk : kb + kk) * g.ldb + n0 + nc);
             }
         }
+        // rows 8 (t % 8) + i of a transposed operand, k = KS (t / 8) .. + KS - 1
+        auto put_transposed = [&](bf16_t *sT, const uint4 (&v)[KS]) {
+            const int rc = (t & 7) * 8, kq = KS * (t >> 3);
 #pragma unroll
-        for (int sl = 0; sl < KS; ++sl) {
-            if (!TA) {
-                const int r = t >> 2, kq = (t & 3) * 8;
-                *reinterpret_cast<uint4 *>(&sA[r * LK + 32 * sl + kq]) = va[sl];
-            } else {
-                const int kk = t >> 3, mc = (t & 7) * 8;
-                const bf16_t *e = reinterpret_cast<const bf16_t *>(&va[sl]);
+            for (int i = 0; i < 8; ++i) {
+                uint32_t w[KS / 2 > 0 ? KS / 2 : 1];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) sA[(mc + i) * LK + 32 * sl + kk] = e[i];
+                for (int r = 0; r < KS / 2; ++r) {
+                    // element i of k = kq + 2r (low half) and of k = kq + 2r + 1 (high half)
+                    const uint32_t lo = reinterpret_cast<const uint32_t *>(&v[2 * r])[i >> 1];
+                    const uint32_t hi = reinterpret_cast<const uint32_t *>(&v[2 * r + 1])[i >> 1];
+                    w[r] = (i & 1) ? ((lo >> 16) | (hi & 0xFFFF0000u)) : ((lo & 0xFFFFu) | (hi << 16));
+                }
+                if constexpr (KS == 4)
+                    *reinterpret_cast<uint2 *>(&sT[lds(rc + i, kq)]) = uint2{w[0], w[1]};
+                else
+                    *reinterpret_cast<uint32_t *>(&sT[lds(rc + i, kq)]) = w[0];
             }
-            if (!TB) {
-                const int c = t >> 2, kq = (t & 3) * 8;
-                *reinterpret_cast<uint4 *>(&sB[c * LK + 32 * sl + kq]) = vb[sl];
-            } else {
-                const int kk = t >> 3, nc = (t & 7) * 8;
-                const bf16_t *e = reinterpret_cast<const bf16_t *>(&vb[sl]);
+        };
+        if constexpr (TA && KS > 1) {
+            put_transposed(sA, va);
+        } else {
 #pragma unroll
-                for (int i = 0; i < 8; ++i) sB[(nc + i) * LK + 32 * sl + kk] = e[i];
+            for (int sl = 0; sl < KS; ++sl) {
+                if (!TA) {
+                    const int r = t >> 2, kq = (t & 3) * 8;
+                    *reinterpret_cast<uint4 *>(&sA[lds(r, 32 * sl + kq)]) = va[sl];
+                } else {
+                    const int kk = t >> 3, mc = (t & 7) * 8;
+                    const bf16_t *e = reinterpret_cast<const bf16_t *>(&va[sl]);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) sA[lds(mc + i, 32 * sl + kk)] = e[i];
+                }
+            }
+        }
+        if constexpr (TB && KS > 1) {
+            put_transposed(sB, vb);
+        } else {
+#pragma unroll
+            for (int sl = 0; sl < KS; ++sl) {
+                if (!TB) {
+                    const int c = t >> 2, kq = (t & 3) * 8;
+                    *reinterpret_cast<uint4 *>(&sB[lds(c, 32 * sl + kq)]) = vb[sl];
+                } else {
+                    const int kk = t >> 3, nc = (t & 7) * 8;
+                    const bf16_t *e = reinterpret_cast<const bf16_t *>(&vb[sl]);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) sB[lds(nc + i, 32 * sl + kk)] = e[i];
+                }
             }
         }
         __syncthreads();
@@ -194,10 +236,10 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
             bf16x8 af[2], bfr[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
-                af[i] = *reinterpret_cast<const bf16x8 *>(&sA[(wm + 16 * i + fr) * LK + 32 * sl + fk]);
+                af[i] = *reinterpret_cast<const bf16x8 *>(&sA[lds(wm + 16 * i + fr, 32 * sl + fk)]);
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                bfr[j] = *reinterpret_cast<const bf16x8 *>(&sB[(wn + 16 * j + fr) * LK + 32 * sl + fk]);
+                bfr[j] = *reinterpret_cast<const bf16x8 *>(&sB[lds(wn + 16 * j + fr, 32 * sl + fk)]);
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -206,7 +248,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
         }
         if (rowsum) {                    // row t/4 of the A tile, a quarter of its k
 #pragma unroll
-            for (int i = 0; i < TKT / 4; ++i) bsum += bf2f(sA[(t >> 2) * LK + (t & 3) * (TKT / 4) + i]);
+            for (int i = 0; i < TKT / 4; ++i) bsum += bf2f(sA[lds(t >> 2, (t & 3) * (TKT / 4) + i)]);
         }
         __syncthreads();
     }
