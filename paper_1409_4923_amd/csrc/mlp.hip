@@ -407,10 +407,8 @@ GemmArgs gemm_args()
 constexpr int FROWS = 128;             // rows per work-group
 constexpr int INFER_RT = 2;            // row tiles of 16 per wave
 constexpr int INFER_BT = 256;          // 4 waves per work-group
-constexpr int SK = 32;                 // row of a staged k slice (bf16), 8-byte units swizzled
+constexpr int SK = 32;                 // row of a staged k slice (bf16), 16-byte pairs swizzled
 constexpr int NSLICE = 16;             // k slices of the two 256 x 256 layers
-
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ __bf16 to_bf(float f) { return (__bf16)f; }   // v_cvt_pk_bf16_f32 (RNE)
 
@@ -451,10 +449,12 @@ __global__ void __launch_bounds__(INFER_BT, 2) k_mlp_infer(const float *x, uint6
             v[i] = *reinterpret_cast<const uint4 *>(W + (uint64_t)(u >> 2) * H + (u & 3) * 8);
         }
     };
-    // In LDS, 8-byte unit p (k columns 4p .. 4p + 3) of row r sits at position
-    // p ^ ((r >> 1) & 7): the 16 rows a fragment read touches then hit 16 different
-    // bank pairs for every lane group (no bank conflicts).  Inside the k loop a slice
-    // is staged in two halves of UNITS / 2 units per thread.
+    // In LDS a slice row holds four 16-byte pairs: pair p is 8-byte unit p (k columns
+    // 4p .. 4p + 3) followed by unit p + 4, which is exactly one lane group's A
+    // fragment (one 16-byte read, no register shuffling), and it sits at position
+    // p ^ ((r >> 1) & 3) of row r, so the 8 lanes a read serves at a time hit
+    // different banks.  Inside the k loop a slice is staged in two halves of
+    // UNITS / 2 units per thread.
     auto load_half = [&](int T, int hf, uint4 (&v)[UNITS / 2]) {
         const bf16_t *W = WB + (T < 8 ? BOFF_W2 : BOFF_W3) + 32 * (T & 7);
 #pragma unroll
@@ -467,18 +467,20 @@ __global__ void __launch_bounds__(INFER_BT, 2) k_mlp_infer(const float *x, uint6
 #pragma unroll
         for (int i = 0; i < UNITS / 2; ++i) {
             const int u = t + (i + hf * UNITS / 2) * BT;
-            const int r = u >> 2, q = u & 3, h = (r >> 1) & 7;
-            *reinterpret_cast<uint2 *>(&sW[buf][r * SK + ((2 * q) ^ h) * 4]) = uint2{v[i].x, v[i].y};
-            *reinterpret_cast<uint2 *>(&sW[buf][r * SK + ((2 * q + 1) ^ h) * 4]) = uint2{v[i].z, v[i].w};
+            const int r = u >> 2, q = u & 3, f = (r >> 1) & 3;
+            const int p0 = (2 * q) & 3, p1 = (2 * q + 1) & 3, hf = q >> 1;   // units 2q, 2q + 1
+            *reinterpret_cast<uint2 *>(&sW[buf][r * SK + (p0 ^ f) * 8 + 4 * hf]) = uint2{v[i].x, v[i].y};
+            *reinterpret_cast<uint2 *>(&sW[buf][r * SK + (p1 ^ f) * 8 + 4 * hf]) = uint2{v[i].z, v[i].w};
         }
     };
     auto store_slice = [&](int buf, const uint4 (&v)[UNITS]) {
 #pragma unroll
         for (int i = 0; i < UNITS; ++i) {
             const int u = t + i * BT;
-            const int r = u >> 2, q = u & 3, h = (r >> 1) & 7;
-            *reinterpret_cast<uint2 *>(&sW[buf][r * SK + ((2 * q) ^ h) * 4]) = uint2{v[i].x, v[i].y};
-            *reinterpret_cast<uint2 *>(&sW[buf][r * SK + ((2 * q + 1) ^ h) * 4]) = uint2{v[i].z, v[i].w};
+            const int r = u >> 2, q = u & 3, f = (r >> 1) & 3;
+            const int p0 = (2 * q) & 3, p1 = (2 * q + 1) & 3, hf = q >> 1;   // units 2q, 2q + 1
+            *reinterpret_cast<uint2 *>(&sW[buf][r * SK + (p0 ^ f) * 8 + 4 * hf]) = uint2{v[i].x, v[i].y};
+            *reinterpret_cast<uint2 *>(&sW[buf][r * SK + (p1 ^ f) * 8 + 4 * hf]) = uint2{v[i].z, v[i].w};
         }
     };
     uint4 pv[UNITS];
@@ -533,18 +535,15 @@ __global__ void __launch_bounds__(INFER_BT, 2) k_mlp_infer(const float *x, uint6
         // matrix cores fed from this wave while the other group's wave on the SIMD
         // works through its VALU epilogue.
         __builtin_amdgcn_s_setprio(1);
-        // lane (g, c) reads units g and 4 + g of rows 16 ft + c
-        const bf16_t *slo = &sW[T % 3][c * SK + 4 * (g ^ ((c >> 1) & 7))];
-        const bf16_t *shi = &sW[T % 3][c * SK + 4 * ((g ^ ((c >> 1) & 7)) ^ 4)];
+        // lane (g, c) reads pair g (units g and 4 + g) of rows 16 ft + c
+        const bf16_t *sfr = &sW[T % 3][c * SK + 8 * (g ^ ((c >> 1) & 3))];
 #pragma unroll
         for (int ft = 0; ft < 16; ++ft) {
             if (ft == 8 && T + 2 < NSLICE) {
                 store_half((T + 2) % 3, 0, ph);
                 load_half(T + 2, 1, ph);
             }
-            const bf16x4 lo = *reinterpret_cast<const bf16x4 *>(slo + 16 * ft * SK);
-            const bf16x4 hi = *reinterpret_cast<const bf16x4 *>(shi + 16 * ft * SK);
-            const bf16x8 a = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(sfr + 16 * ft * SK);
             // the accumulators start at the bias of their output features
             const floatx4 bias = *reinterpret_cast<const floatx4 *>(&sB[T >> 3][16 * ft + 4 * g]);
 #pragma unroll
