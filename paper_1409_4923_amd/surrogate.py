@@ -79,8 +79,9 @@ def adaptive_monte_carlo(x: np.ndarray, tol: float, periods: int, pilot: int = 6
     paths per row, then up to rounds - 1 top-up scans.  Before each top-up, row i's
     spread s_i (of all its paths so far) sets its total N_i = ceil((3 s_i / tol)^2),
     at most max_paths (a row without a finite spread takes max_paths); rows short of
-    N_i run the difference on streams of their own (seed + round), and the samples are
-    pooled.  Seconds and path-steps count every scan."""
+    N_i run the difference on streams of their own (seed + round, so the call uses
+    seeds seed .. seed + rounds - 1 at these point ids), and the samples are pooled.
+    Seconds and path-steps count every scan."""
     x = np.asarray(x)
     res = monte_carlo(x, pilot, periods, seed, first_point, tune)
     n = res.n_paths.astype(np.float64)
