@@ -395,11 +395,31 @@ def stats_from_bytes(b: bytes) -> bm_stats:
 # Batched scan
 # ---------------------------------------------------------------------------
 def _arrays(models, runs):
+    """ctypes arrays of the records: passed through when given as such (see
+    record_arrays), else built from sequences of bm_model / bm_run."""
     n = len(models)
     assert n == len(runs) and n > 0
+    if isinstance(models, ctypes.Array) and isinstance(runs, ctypes.Array):
+        return models, runs, n
     M = (bm_model * n)(*models)
     R = (bm_run * n)(*runs)
     return M, R, n
+
+
+def record_arrays(n: int):
+    """Zeroed numpy record arrays of n bm_model and n bm_run records (the sizes and the
+    defaults of make_model / make_run filled in), and ctypes arrays over the same memory
+    for the scan calls: fill the numpy columns, then pass the ctypes arrays."""
+    import numpy as np
+    mo = np.zeros(n, dtype=np.dtype(bm_model))
+    ru = np.zeros(n, dtype=np.dtype(bm_run))
+    mo["size"] = ctypes.sizeof(bm_model)
+    for f in ("gamma", "drive_omega", "dich_mua", "dich_mub", "shot_rate"):
+        mo[f] = 1.0
+    ru["size"] = ctypes.sizeof(bm_run)
+    ru["x0_hi"] = 1.0
+    ru["n_paths"] = 1
+    return mo, ru, (bm_model * n).from_buffer(mo), (bm_run * n).from_buffer(ru)
 
 
 def bm_scan_workspace_size(models, runs) -> int:
@@ -502,7 +522,8 @@ class Scan:
         import torch
         self.torch = torch
         self.device = torch.device("cuda") if device is None else torch.device(device)
-        self.models, self.runs = list(models), list(runs)
+        self.models = models if isinstance(models, ctypes.Array) else list(models)
+        self.runs = runs if isinstance(runs, ctypes.Array) else list(runs)
         self.n = len(self.models)
         self.ws_bytes = bm_scan_workspace_size(self.models, self.runs)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
@@ -517,6 +538,13 @@ class Scan:
     def stats(self):
         self.stream.synchronize()
         return stats_array_from_bytes(self.results.cpu().numpy().tobytes(), self.n)
+
+    def stats_records(self):
+        """The per-point bm_stats as a numpy record array (fields n, n_nonfinite, mean,
+        var, se, t_window)."""
+        import numpy as np
+        self.stream.synchronize()
+        return np.frombuffer(self.results.cpu().numpy().tobytes(), dtype=np.dtype(bm_stats), count=self.n)
 
     def close(self):
         if getattr(self, "h", None):

@@ -5,7 +5,6 @@ bm_mlp_backward, bm_mlp_adam_step, bm_surrogate_query).
 """
 from __future__ import annotations
 
-import math
 import time
 from dataclasses import dataclass
 
@@ -32,6 +31,25 @@ def point_workloads(x: np.ndarray, n_paths, periods: int, seed: int = 0, first_p
     return out
 
 
+def point_records(x: np.ndarray, n_paths, periods: int, seed: int = 0, first_point: int = 0):
+    """The records of point_workloads built column-wise: (numpy models, numpy runs,
+    ctypes models, ctypes runs) over the same memory, for a scan over many points."""
+    x = np.asarray(x, dtype=np.float64)
+    n = len(x)
+    mo, ru, M, R = B.record_arrays(n)
+    n_steps = periods * SPP
+    mo["dyn"], mo["pot"], mo["noise"] = W.INERTIAL, W.POT_SIN, W.GAUSS
+    mo["drive_amp"], mo["drive_omega"], mo["force"], mo["D"], mo["gamma"] = x[:, 0], x[:, 1], x[:, 2], x[:, 3], x[:, 4]
+    mo["shot_mean"] = 0.0
+    ru["prec"], ru["steps_per_period"] = W.F32, SPP
+    ru["point_id"] = first_point + np.arange(n, dtype=np.uint64)
+    ru["n_steps"], ru["window_start"] = n_steps, n_steps // 2
+    ru["n_paths"] = np.broadcast_to(np.asarray(n_paths, dtype=np.int64), (n,))
+    ru["seed"] = seed
+    ru["x0_lo"], ru["x0_hi"], ru["v0_lo"], ru["v0_hi"] = 0.0, 1.0, -2.0, 2.0
+    return mo, ru, M, R
+
+
 @dataclass
 class MCResult:
     mean: np.ndarray
@@ -55,22 +73,22 @@ def pool(n1, m1, s1, n2, m2, s2):
 def monte_carlo(x: np.ndarray, n_paths, periods: int, seed: int = 0, first_point: int = 0,
                 tune=None) -> MCResult:
     """<v> of every row by one batched scan (plan + one graph launch); n_paths is one
-    count for every row or one per row."""
+    count for every row or one per row.  Seconds run from building the records to the
+    statistics on the host."""
     import torch
-    pts = point_workloads(x, n_paths, periods, seed, first_point)
-    mr = [W.to_c(w) for w in pts]
     t0 = time.perf_counter()
-    sc = B.Scan([m for m, _ in mr], [r for _, r in mr], tune=tune)
+    _, ru, M, R = point_records(x, n_paths, periods, seed, first_point)
+    sc = B.Scan(M, R, tune=tune)
     sc.launch()
-    st = sc.stats()
+    st = sc.stats_records()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     sc.close()
-    mean = np.array([s.mean for s in st])
-    se = np.array([s.se for s in st])
-    std = np.array([math.sqrt(s.var) if s.n > 1 else float("nan") for s in st])
-    counts = np.array([w.n_paths for w in pts], dtype=np.int64)
-    return MCResult(mean, se, std, el, sum(w.path_steps() for w in pts), counts)
+    mean = st["mean"].astype(np.float64)
+    se = st["se"].astype(np.float64)
+    std = np.where(st["n"] > 1, np.sqrt(np.maximum(st["var"], 0.0)), np.nan)
+    counts = ru["n_paths"].astype(np.int64)
+    return MCResult(mean, se, std, el, int(np.sum(counts)) * periods * SPP, counts)
 
 
 def adaptive_monte_carlo(x: np.ndarray, tol: float, periods: int, pilot: int = 64, max_paths: int = 1 << 16,

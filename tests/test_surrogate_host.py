@@ -33,3 +33,19 @@ def test_calibrate_threshold_picks_the_largest_qualifying_threshold():
         assert row["answered"] == k.mean()
     assert t < grid[-1]                                  # the largest spreads do not qualify
     assert S.calibrate_threshold(std, err, 1e-6, grid)[0] is None
+
+
+def test_point_records_equal_the_workload_records():
+    """The column-wise records of a scan over many points hold the same bytes as the
+    per-point Workload path."""
+    import ctypes
+    from paper_1409_4923_amd import workloads as W
+    x = W.surrogate_queries(37, seed=4)
+    counts = np.arange(37) * 3 + 64
+    _, _, M, R = S.point_records(x, counts, 7, seed=11, first_point=1000)
+    for i, w in enumerate(S.point_workloads(x, counts, 7, seed=11, first_point=1000)):
+        m, r = W.to_c(w)
+        assert ctypes.string_at(ctypes.addressof(M[i]), ctypes.sizeof(m)) == \
+            ctypes.string_at(ctypes.addressof(m), ctypes.sizeof(m))
+        assert ctypes.string_at(ctypes.addressof(R[i]), ctypes.sizeof(r)) == \
+            ctypes.string_at(ctypes.addressof(r), ctypes.sizeof(r))
