@@ -123,33 +123,35 @@ def adaptive_monte_carlo(x: np.ndarray, tol: float, periods: int, pilot: int = 6
 
 def train(sur: "B.Surrogate", x: np.ndarray, y: np.ndarray, epochs: int, batch: int = 1024, lr: float = 1e-3,
           seed: int = 0, lr_final: float = 1e-4):
-    """Minibatch Adam on the mean squared error; member m draws its own minibatches
-    (a bootstrap of the training rows).  Returns the per-epoch mean member loss."""
+    """Minibatch Adam on the mean squared error; member m trains on its own bootstrap
+    sample of the rows (n rows drawn with replacement), visited in a fresh order every
+    epoch.  One permutation of the positions per epoch serves all members: member m's
+    rows at those positions are independent of the other members' because the
+    bootstrap draws are.  Returns the per-epoch mean member loss."""
     import torch
     rng = np.random.default_rng(seed)
     n = len(x)
     xd = torch.tensor(np.asarray(x, dtype=np.float32), device=sur.device)
     yd = torch.tensor(np.asarray(y, dtype=np.float32), device=sur.device)
-    boot = rng.integers(0, n, (sur.n, n))
+    boot = rng.integers(0, n, (sur.n, n)).astype(np.int32)
     steps_per_epoch = max(1, n // batch)
     total = epochs * steps_per_epoch
-    hist = []
+    last = []
     k = 0
     for ep in range(epochs):
-        perm = np.stack([rng.permutation(boot[m]) for m in range(sur.n)])
-        # one upload per epoch, laid out [step][member][row] so each step's slice is contiguous
-        perm = perm[:, :steps_per_epoch * batch].reshape(sur.n, steps_per_epoch, batch).transpose(1, 0, 2)
-        perm_d = torch.tensor(np.ascontiguousarray(perm, dtype=np.int32), device=sur.device)
-        losses = []
+        pos = rng.permutation(n)[:steps_per_epoch * batch]
+        # one upload per epoch, laid out [step][member][row] so each step's slice is
+        # contiguous; from pinned memory without waiting, so the host prepares the next
+        # epoch while the device runs this one (nothing synchronises until the end)
+        perm = boot[:, pos].reshape(sur.n, steps_per_epoch, batch).transpose(1, 0, 2)
+        perm_d = torch.from_numpy(np.ascontiguousarray(perm)).pin_memory().to(sur.device, non_blocking=True)
         for s in range(steps_per_epoch):
             loss = sur.backward(xd, yd, perm_d[s])
             frac = k / max(1, total - 1)
             sur.adam(lr * (lr_final / lr) ** frac)        # exponential decay to lr_final
             k += 1
-            if s == steps_per_epoch - 1:
-                losses.append(loss)
-        hist.append(float(torch.stack(losses).mean().item()))
-    return hist
+        last.append(loss)                                 # the epoch's last step, per member
+    return [float(v) for v in torch.stack(last).mean(dim=1).cpu()] if last else []
 
 
 def uncertain_points(sur: "B.Surrogate", x: np.ndarray, n_pick: int, threshold: float) -> np.ndarray:
