@@ -134,3 +134,30 @@ def test_adaptive_monte_carlo_meets_its_tolerance():
     assert np.mean(z <= 3) >= 0.95
     # the budget follows the spread: a uniform count at the largest need costs more
     assert np.sum(ad.n_paths) < len(x) * np.max(ad.n_paths)
+
+
+def test_query_with_sequential_fallback():
+    """query(tol=...) answers the rows the ensemble routes with the sequential Monte Carlo
+    budget and leaves the others at the ensemble mean; the routed rows agree with an
+    independent 16384-path scan within 3 combined SE (95% of them)."""
+    import torch
+    tol, periods = 0.02, 50
+    sur = B.Surrogate(5, seed=3)                   # untrained: the spreads are wide
+    x = W.surrogate_queries(96, seed=41)
+    _, sd0, _, _ = sur.query(torch.tensor(x, device="cuda"), 1.0)
+    thr = float(np.median(sd0.cpu().numpy()))      # about half of the rows routed
+    q = S.query(sur, x, thr, None, periods, seed=7, mc_first_point=1 << 27, tol=tol)
+    mean, std, _, fcnt = sur.query(torch.tensor(x, device="cuda"), thr)
+    mean, std = mean.cpu().numpy().astype(np.float64), std.cpu().numpy()
+    routed = np.nonzero(~(std <= thr))[0]
+    assert np.array_equal(np.sort(q.fallback), routed) and len(routed) == int(fcnt.item())
+    kept = np.setdiff1d(np.arange(len(x)), routed)
+    assert np.array_equal(q.value[kept], mean[kept])
+    assert 0 < len(routed) < len(x)
+    ad = S.adaptive_monte_carlo(x[routed], tol, periods, seed=7, first_point=1 << 27)
+    assert np.array_equal(q.value[routed], ad.mean)      # the same streams, the same budget
+    truth = S.monte_carlo(x[routed], 1 << 14, periods, seed=19, first_point=1 << 27)
+    z = np.abs(ad.mean - truth.mean) / np.sqrt(ad.se ** 2 + truth.se ** 2)
+    say("query with sequential fallback: %d of %d routed, %.3f within 3 combined SE"
+        % (len(routed), len(x), np.mean(z <= 3)))
+    assert np.mean(z <= 3) >= 0.95
